@@ -1,0 +1,238 @@
+"""Benchmark of FE sparse-matrix assembly on one MI355X.
+
+Workload (default): the 64^3 trilinear hex mesh, 3 DOFs per node (823 875
+DOFs, 262 144 elements), 24 x 24 FP64 SPD element matrices (B B^T/24 + I,
+seed 0); CSR and CRAC patterns built once on the device.
+
+A step is one numeric assembly of all 262 144 element matrices into the
+global values array (reset + scatter-add), with inputs resident in HBM.
+`value` is element matrices assembled per second for the fastest full
+assembly variant; every variant is reported under "variants", value-only
+re-assembly latency under "reassembly_ms", the symbolic phase under
+"pattern_build_ms".  Progress goes to stderr; stdout gets one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload hex64|quad64|tet40]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("element matrices assembled/s + effective HBM GB/s (64³ hex); "
+          "p50/p99 reassembly")
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def stats(ms):
+    a = np.asarray(ms, dtype=np.float64)
+    return {"mean": float(a.mean()), "min": float(a.min()), "p50": float(np.percentile(a, 50)),
+            "p99": float(np.percentile(a, 99)), "n": int(a.size)}
+
+
+def time_calls(fn, reps, warmup):
+    """Per-call device time (ms) from HIP events on torch's current stream,
+    which is the stream the library launches on."""
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+    for i in range(reps):
+        starts[i].record()
+        fn()
+        ends[i].record()
+    torch.cuda.synchronize()
+    return [s.elapsed_time(e) for s, e in zip(starts, ends)]
+
+
+def workload(name):
+    from fe_inputs import configs
+
+    if name == "hex64":
+        return configs.hex64(), "hex64: 64^3 Q1 hex, 3 DOF/node, 24x24 SPD FP64 Ke, seed 0"
+    if name == "quad64":
+        return configs.quad64(), "quad64: 64^2 Q1 quad, 1 DOF/node, 4x4 zero-row-sum FP64 Ke, seed 0"
+    if name == "tet40":
+        return configs.tet40(), ("tet40: 40^3 cubes x 6 tet10, permuted nodes (seed 0), "
+                                 "3 DOF/node, 30x30 SPD FP64 Ke, seed 0")
+    raise ValueError(name)
+
+
+def algorithmic_bytes(w, p, fmt):
+    """Bytes the method must move per assembly: Ke once, conn once, the
+    format's index arrays once, values read and written once (the reset is
+    counted separately)."""
+    E, k, n = w.n_elem, w.nodes_per_elem, w.n
+    b = E * n * n * 8 + E * k * 4 + 2 * p.nnz * 8
+    if fmt == "csr":
+        b += (p.n_rows + 1) * 4 + p.nnz * 4
+    else:
+        b += (p.n_rows + 1) * 4 + p.n_ca * 4
+    return b
+
+
+def cpu_baseline(w, ke, reps):
+    """The serial oracle's numeric phase on one pinned core."""
+    from oracle import oracle
+
+    rp, ci = oracle.pattern(w.conn, w.dofs_per_node, w.n_nodes)
+    old = os.sched_getaffinity(0)
+    core = min(old)
+    os.sched_setaffinity(0, {core})
+    try:
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            oracle.assemble(w.conn, w.dofs_per_node, ke, rp, ci, with_abs=False)
+            ts.append(time.perf_counter() - t0)
+    finally:
+        os.sched_setaffinity(0, old)
+    mean = float(np.mean(ts))
+    return {"value": w.n_elem / mean, "unit": "element matrices/s", "cores": 1, "kind": "oracle",
+            "sample": (f"whole {w.name} numeric phase (values reset + sequential scatter with "
+                       f"binary search), pattern prebuilt, {reps} reps, pinned to core {core}; "
+                       f"mean {mean * 1e3:.1f} ms, min {min(ts) * 1e3:.1f} ms; host has "
+                       f"{os.cpu_count()} logical CPUs")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="hex64", choices=["hex64", "quad64", "tet40"])
+    ap.add_argument("--cpu-reps", type=int, default=3, help="0 skips the oracle baseline")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(see the sharding design); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2012_00585_amd as feasm
+
+    feasm.load()
+    dev = torch.device("cuda:0")
+    w, wdesc = workload(args.workload)
+    log(f"[bench] {wdesc}: generating element matrices")
+    ke = w.ke()
+    conn_d = torch.from_numpy(w.conn).to(dev)
+    ke_d = torch.from_numpy(ke).to(dev)
+    torch.cuda.synchronize()
+
+    log("[bench] pattern_build")
+    flags = feasm.BUILD_CSR | feasm.BUILD_CRAC | feasm.BUILD_COLOUR
+    pb_ms = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        p = feasm.pattern_build(conn_d, w.dofs_per_node, w.n_nodes, flags)
+        pb_ms.append((time.perf_counter() - t0) * 1e3)
+        if _ < 2:
+            p.free()
+    values = torch.zeros(p.nnz, dtype=torch.float64, device=dev)
+
+    A, C, ACC = feasm.SCATTER_ATOMIC, feasm.SCATTER_COLOURED, feasm.ACCUMULATE
+    full = {
+        "csr_atomic": lambda: feasm.assemble_csr(p, ke_d, values, A),
+        "crac_atomic": lambda: feasm.assemble_crac(p, ke_d, values, A),
+        "csr_coloured": lambda: feasm.assemble_csr(p, ke_d, values, C),
+        "crac_coloured": lambda: feasm.assemble_crac(p, ke_d, values, C),
+    }
+    scatter_only = {
+        "csr_atomic": lambda: feasm.assemble_csr(p, ke_d, values, A | ACC),
+        "crac_atomic": lambda: feasm.assemble_crac(p, ke_d, values, A | ACC),
+        "csr_coloured": lambda: feasm.assemble_csr(p, ke_d, values, C | ACC),
+        "crac_coloured": lambda: feasm.assemble_crac(p, ke_d, values, C | ACC),
+    }
+    reps = max(args.steps, 5)
+    variants = {}
+    for name, fn in full.items():
+        log(f"[bench] variant {name}")
+        t_full = stats(time_calls(fn, reps, args.warmup))
+        t_sc = stats(time_calls(scatter_only[name], reps, args.warmup))
+        fmt = name.split("_")[0]
+        nbytes = algorithmic_bytes(w, p, fmt)
+        variants[name] = {
+            "assemble_ms": t_full,
+            "scatter_only_ms": t_sc,
+            "elements_per_s": w.n_elem / (t_full["mean"] * 1e-3),
+            "algorithmic_bytes": nbytes,
+            "effective_GBps": nbytes / (t_full["mean"] * 1e-3) / 1e9,
+            "scatter_GBps": nbytes / (t_sc["mean"] * 1e-3) / 1e9,
+        }
+    log("[bench] value-only re-assembly latency")
+    reasm = {}
+    for name, fmt in (("csr_atomic", feasm.FMT_CSR), ("crac_atomic", feasm.FMT_CRAC)):
+        fn = (lambda f=fmt: feasm.reassemble_values(p, f, ke_d, values, A))
+        reasm[name] = stats(time_calls(fn, max(reps, 50), args.warmup))
+
+    best = min(variants, key=lambda k: variants[k]["assemble_ms"]["mean"])
+    step = full[best]
+    log(f"[bench] timed steps: {best} x {args.steps}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(args.steps):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    ms_per_step = t0.elapsed_time(t1) / args.steps
+
+    v = variants[best]
+    fmt = best.split("_")[0]
+    kernel_ms = v["scatter_only_ms"]["mean"]
+    achieved = v["algorithmic_bytes"] / (kernel_ms * 1e-3) / 1e9
+    line = {
+        "metric": METRIC,
+        "value": w.n_elem / (ms_per_step * 1e-3),
+        "unit": "element matrices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wdesc, "n_elem": w.n_elem, "n_rows": p.n_rows, "nnz": p.nnz,
+                   "n_ca": p.n_ca, "n_colours": p.n_colours, "step_variant": best,
+                   "step": "values reset + scatter-add of every element matrix"},
+        "effective_GBps": v["algorithmic_bytes"] / (ms_per_step * 1e-3) / 1e9,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"k_assemble ({best}, scatter only, one launch)",
+                     "kernel_ms": kernel_ms},
+        "reassembly_ms": reasm,
+        "pattern_build_ms": {"runs": pb_ms},
+        "variants": variants,
+    }
+    if args.cpu_reps > 0:
+        log("[bench] CPU baseline (serial oracle)")
+        line["cpu_baseline"] = cpu_baseline(w, ke, args.cpu_reps)
+    p.free()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

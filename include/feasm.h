@@ -1,0 +1,180 @@
+/*
+ * feasm: finite-element sparse-matrix assembly on MI355X (gfx950).
+ *
+ * C ABI of libfeasm.so.  The library turns per-element dense FP64 stiffness
+ * matrices into a global sparse matrix, following Sky, Polindara, Muench,
+ * Birk, "A flexible sparse matrix data format and parallel algorithms for
+ * the assembly of sparse matrices in general finite element applications
+ * using atomic synchronisation primitives" (arXiv 2012.00585):
+ *
+ *   symbolic phase  pattern_build   -> CSR and CRAC sparsity structure
+ *   numeric phase   assemble_csr / assemble_crac / reassemble_values
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - An element is a dense n x n matrix K plus its DOF index array D
+ *    (Section 2.1).  With k nodes per element and d DOFs per node,
+ *    n = k*d; DOFs are node-major: local row a*d + c of K maps to global
+ *    DOF d*conn[e][a] + c (the contiguous per-node numbering of Section 2.1).
+ *  - Global matrix G has n_rows = n_cols = d*n_nodes.  Its pattern is the
+ *    union over elements of {(D_e[r], D_e[s])}; columns of a row are sorted
+ *    ascending; no entry is dropped, whatever its value (Section 3 intro).
+ *  - All indices are 0-based.  Pattern arrays are int32; building a pattern
+ *    whose nnz, number of CRAC integers or number of rows reaches 2^31
+ *    fails with FEASM_EOVERFLOW.
+ *  - "dev" pointers are HIP device memory on the current device; "host"
+ *    pointers are ordinary host memory.  Streams are hipStream_t (NULL is
+ *    the legacy default stream).
+ *  - Every call returns a feasm_status.  No C++ exception crosses the ABI.
+ *    last_error() returns a thread-local message for the latest failure.
+ *  - Numeric calls are asynchronous on the given stream; pattern_build
+ *    synchronises with its stream before returning.
+ */
+#ifndef FEASM_H
+#define FEASM_H
+
+#include <hip/hip_runtime_api.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct feasm_pattern feasm_pattern; /* opaque handle */
+
+enum feasm_status {
+    FEASM_OK = 0,
+    FEASM_EINVAL = -1,    /* bad argument (null pointer, non-positive size, unknown flag) */
+    FEASM_ERANGE = -2,    /* a node id outside [0, n_nodes) */
+    FEASM_ENOMEM = -3,    /* device allocation failed */
+    FEASM_EHIP = -4,      /* a HIP runtime call failed */
+    FEASM_EOVERFLOW = -5, /* nnz, CRAC length, rows or element entries reach 2^31 */
+    FEASM_ELIMIT = -6     /* a documented implementation limit is exceeded */
+};
+
+/* pattern_build flags (bitwise or) */
+enum {
+    FEASM_BUILD_CSR = 1,    /* row_ptr[n_rows+1], col_idx[nnz] */
+    FEASM_BUILD_CRAC = 2,   /* crac_row_ptr[n_rows+1], col_align[n_ca] */
+    FEASM_BUILD_COLOUR = 4  /* element colouring for the atomic-free scatter */
+};
+
+/* format selector for reassemble_values */
+enum { FEASM_FMT_CSR = 0, FEASM_FMT_CRAC = 1 };
+
+/* scatter strategy of the numeric calls */
+enum {
+    FEASM_SCATTER_AUTO = 0,     /* the library's choice for this handle */
+    FEASM_SCATTER_ATOMIC = 1,   /* one hardware FP64 atomic add per contribution */
+    FEASM_SCATTER_COLOURED = 2, /* one launch per colour, plain read-modify-write */
+    FEASM_ACCUMULATE = 0x100    /* or-ed into `scatter`: add into `values` without
+                                   resetting it first (values += sum_e scatter(K_e)) */
+};
+
+/*
+ * pattern_build -- symbolic phase (Section 3 intro: the pattern is set up
+ * once, before any assembly; Section 2.2 and Fig. 1 for CSR and CRAC).
+ *
+ *   conn            dev  int32 [n_elem][nodes_per_elem], row-major; read only,
+ *                        copied into the handle, may be freed afterwards.
+ *   n_elem          > 0
+ *   nodes_per_elem  k > 0
+ *   dofs_per_node   d > 0
+ *   n_nodes         > 0; every conn entry must lie in [0, n_nodes)
+ *   build_flags     FEASM_BUILD_* bits, at least one of CSR and CRAC
+ *   out             host; receives the new handle (NULL on failure)
+ *
+ * CSR (Section 2.2, Fig. 1c): row_ptr[i] = entries in rows < i, col_idx
+ * sorted within each row.  CRAC (Section 2.2, Fig. 1d): for each maximal
+ * run of consecutive columns of a row, the pair (first column, position of
+ * its first value in the CSR values array), row by row; crac_row_ptr counts
+ * integers of col_align (two per run); a final pair (n_cols, nnz) closes
+ * col_align, so n_ca = 2*runs + 2.  CRAC shares the CSR values layout.
+ *
+ * Colouring (Section 3.3): elements sharing a node get different colours;
+ * the element list is grouped by colour, increasing element id within a
+ * colour.
+ *
+ * Errors: EINVAL for bad arguments; ERANGE if a node id is out of range
+ * (checked on the device, reported before returning); EOVERFLOW for int32
+ * overflow of the pattern; ELIMIT if a node is shared by so many elements
+ * that its candidate column list exceeds 32768 entries; ENOMEM; EHIP.
+ * Synchronises `stream` before returning, so no asynchronous error is lost.
+ */
+int pattern_build(const int32_t* conn, int64_t n_elem, int32_t nodes_per_elem,
+                  int32_t dofs_per_node, int64_t n_nodes, uint32_t build_flags,
+                  hipStream_t stream, feasm_pattern** out);
+
+/*
+ * assemble_csr / assemble_crac -- numeric phase (Section 3: values are reset
+ * to zero, then every element matrix is added, G(D(r),D(s)) += K(r,s), as in
+ * the sequential, atomic and colouring listings).
+ *
+ *   p        handle from pattern_build (built with CSR, resp. CRAC; the
+ *            coloured strategy also needs FEASM_BUILD_COLOUR)
+ *   ke       dev  double [n_elem][n][n], row-major, element order of conn
+ *   values   dev  double [nnz]; overwritten with sum_e scatter(K_e)
+ *   scatter  FEASM_SCATTER_*, optionally | FEASM_ACCUMULATE (no reset: the
+ *            sums are added to what `values` holds, e.g. to assemble several
+ *            element blocks into one matrix)
+ *
+ * assemble_csr finds positions by binary search of col_idx in each row;
+ * assemble_crac by linear block search over the row's CRAC pairs (Section
+ * 2.2 listing) followed by contiguous slice adds over the element's DOF runs
+ * (Section 3.3).  Both produce the same values array.
+ *
+ * Asynchronous on `stream`; nothing is checked on the device.  The caller
+ * guarantees buffer sizes and that `values` does not alias `ke`; concurrent
+ * calls on one values buffer race.  Returns EINVAL for a null handle or
+ * buffer, a format the handle lacks, or an unknown strategy.
+ */
+int assemble_csr(const feasm_pattern* p, const double* ke, double* values, int scatter,
+                 hipStream_t stream);
+int assemble_crac(const feasm_pattern* p, const double* ke, double* values, int scatter,
+                  hipStream_t stream);
+
+/*
+ * reassemble_values -- value-only re-assembly on an existing pattern
+ * (Section 3 intro: between assemblies the values are reset to zero and the
+ * pattern is kept).  `fmt` is FEASM_FMT_CSR or FEASM_FMT_CRAC.  Returns the
+ * same values as assemble_<fmt> with the same arguments (bitwise for the
+ * coloured strategy; within FP64 reordering for the atomic one).  The first
+ * call may build a per-handle lookup cache on the device (hence the
+ * non-const handle); calls on one handle must not overlap.  Asynchronous.
+ */
+int reassemble_values(feasm_pattern* p, int fmt, const double* ke, double* values, int scatter,
+                      hipStream_t stream);
+
+/* Sizes of the pattern.  Any output pointer may be NULL. */
+int pattern_info(const feasm_pattern* p, int64_t* n_rows, int64_t* nnz, int64_t* n_ca,
+                 int32_t* n_colours);
+
+/*
+ * Borrowed device pointers to the pattern arrays (valid until pattern_free;
+ * NULL for a format that was not built): row_ptr[n_rows+1], col_idx[nnz],
+ * crac_row_ptr[n_rows+1], col_align[n_ca].  Any output may be NULL.
+ */
+int pattern_arrays(const feasm_pattern* p, const int32_t** row_ptr, const int32_t** col_idx,
+                   const int32_t** crac_row_ptr, const int32_t** col_align);
+
+/*
+ * Colouring of a handle built with FEASM_BUILD_COLOUR.  colour_ptr is a
+ * borrowed HOST array [n_colours+1] of offsets into colour_elems, a borrowed
+ * DEVICE array [n_elem] of element ids grouped by colour; element_colour is
+ * a borrowed DEVICE array [n_elem].  Any output may be NULL.
+ */
+int pattern_colouring(const feasm_pattern* p, const int64_t** colour_ptr,
+                      const int32_t** colour_elems, const int32_t** element_colour);
+
+/* Releases the handle and its device arrays (synchronises the device). NULL is ignored. */
+void pattern_free(feasm_pattern* p);
+
+/* Thread-local message describing the latest failed call on this thread. */
+const char* last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FEASM_H */

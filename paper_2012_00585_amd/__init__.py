@@ -1,0 +1,193 @@
+"""feasm: MI355X-native finite-element sparse-matrix assembly (CSR + CRAC).
+
+Python binding of libfeasm.so.  It only marshals arguments: every step of
+the symbolic and numeric phases runs in the library's HIP kernels.  Tensors
+are torch CUDA (HIP) tensors; streams default to torch's current stream.
+
+    p = pattern_build(conn, dofs_per_node=3, n_nodes=nn)          # symbolic
+    values = assemble_csr(p, ke)                                  # numeric
+    values = assemble_crac(p, ke, values)
+    values = reassemble_values(p, FMT_CRAC, ke_new, values)       # values only
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import FeasmError
+
+BUILD_CSR = 1
+BUILD_CRAC = 2
+BUILD_COLOUR = 4
+FMT_CSR = 0
+FMT_CRAC = 1
+SCATTER_AUTO = 0
+SCATTER_ATOMIC = 1
+SCATTER_COLOURED = 2
+ACCUMULATE = 0x100  # or into `scatter`: add into values without resetting them
+
+_HIP_D2D = 3  # hipMemcpyDeviceToDevice
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _require(t, dtype, name):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor, got {t.device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Pattern:
+    """Handle of a sparsity pattern built on the device (owns device arrays)."""
+
+    def __init__(self, handle, n_elem, nodes_per_elem, dofs_per_node, n_nodes, flags):
+        self._h = handle
+        self.n_elem = n_elem
+        self.nodes_per_elem = nodes_per_elem
+        self.dofs_per_node = dofs_per_node
+        self.n = nodes_per_elem * dofs_per_node
+        self.n_nodes = n_nodes
+        self.flags = flags
+        n_rows, nnz, n_ca = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        n_col = ctypes.c_int32()
+        _lib.check(_lib.load().pattern_info(handle, ctypes.byref(n_rows), ctypes.byref(nnz),
+                                            ctypes.byref(n_ca), ctypes.byref(n_col)),
+                   "pattern_info")
+        self.n_rows = n_rows.value
+        self.nnz = nnz.value
+        self.n_ca = n_ca.value
+        self.n_colours = n_col.value
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("pattern was freed")
+        return self._h
+
+    def _copy(self, ptr, count, dtype, stream=None):
+        out = torch.empty(count, dtype=dtype, device="cuda")
+        if count:
+            rc = _lib.hip().hipMemcpyAsync(_ptr(out), ptr, count * out.element_size(), _HIP_D2D,
+                                          _stream(stream))
+            if rc != 0:
+                raise RuntimeError(f"hipMemcpyAsync failed: {rc}")
+        return out
+
+    def _arrays(self):
+        ptrs = [ctypes.c_void_p() for _ in range(4)]
+        _lib.check(_lib.load().pattern_arrays(self.handle, *[ctypes.byref(p) for p in ptrs]),
+                   "pattern_arrays")
+        return ptrs
+
+    def csr(self, stream=None):
+        """Copies of (row_ptr[n_rows+1], col_idx[nnz]) as int32 device tensors."""
+        rp, ci, _, _ = self._arrays()
+        if not rp.value:
+            raise ValueError("pattern was built without CSR")
+        return (self._copy(rp, self.n_rows + 1, torch.int32, stream),
+                self._copy(ci, self.nnz, torch.int32, stream))
+
+    def crac(self, stream=None):
+        """Copies of (crac_row_ptr[n_rows+1], col_align[n_ca]) as int32 device tensors."""
+        _, _, crp, ca = self._arrays()
+        if not crp.value:
+            raise ValueError("pattern was built without CRAC")
+        return (self._copy(crp, self.n_rows + 1, torch.int32, stream),
+                self._copy(ca, self.n_ca, torch.int32, stream))
+
+    def colouring(self, stream=None):
+        """(colour_ptr list[n_colours+1], colour_elems int32[n_elem], element_colour int32[n_elem])."""
+        cp, ce, ec = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        _lib.check(_lib.load().pattern_colouring(self.handle, ctypes.byref(cp), ctypes.byref(ce),
+                                                 ctypes.byref(ec)), "pattern_colouring")
+        cp = ctypes.cast(cp, ctypes.POINTER(ctypes.c_int64))
+        ptr = [cp[i] for i in range(self.n_colours + 1)]
+        return (ptr, self._copy(ce, self.n_elem, torch.int32, stream),
+                self._copy(ec, self.n_elem, torch.int32, stream))
+
+    def free(self):
+        if self._h is not None:
+            _lib.load().pattern_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def pattern_build(conn: torch.Tensor, dofs_per_node: int, n_nodes: int,
+                  flags: int = BUILD_CSR | BUILD_CRAC, stream=None) -> Pattern:
+    """Symbolic phase: CSR/CRAC pattern (and optional colouring) of a mesh.
+
+    ``conn`` is an int32 device tensor [n_elem, nodes_per_elem].
+    """
+    _require(conn, torch.int32, "conn")
+    if conn.dim() != 2:
+        raise ValueError("conn must be [n_elem, nodes_per_elem]")
+    E, k = conn.shape
+    h = ctypes.c_void_p()
+    _lib.check(_lib.load().pattern_build(_ptr(conn), E, k, dofs_per_node, n_nodes, flags,
+                                         _stream(stream), ctypes.byref(h)), "pattern_build")
+    return Pattern(h, E, k, dofs_per_node, n_nodes, flags)
+
+
+def _numeric_args(p: Pattern, ke, values):
+    _require(ke, torch.float64, "ke")
+    if ke.numel() != p.n_elem * p.n * p.n:
+        raise ValueError(f"ke must hold n_elem*n*n = {p.n_elem * p.n * p.n} values, "
+                         f"got {ke.numel()}")
+    if values is None:
+        values = torch.empty(p.nnz, dtype=torch.float64, device=ke.device)
+    _require(values, torch.float64, "values")
+    if values.numel() < p.nnz:
+        raise ValueError(f"values must hold nnz = {p.nnz} entries, got {values.numel()}")
+    return values
+
+
+def assemble_csr(p: Pattern, ke: torch.Tensor, values: torch.Tensor | None = None,
+                 scatter: int = SCATTER_AUTO, stream=None) -> torch.Tensor:
+    """values := sum_e scatter(K_e) through the CSR arrays (asynchronous)."""
+    values = _numeric_args(p, ke, values)
+    _lib.check(_lib.load().assemble_csr(p.handle, _ptr(ke), _ptr(values), scatter,
+                                        _stream(stream)), "assemble_csr")
+    return values
+
+
+def assemble_crac(p: Pattern, ke: torch.Tensor, values: torch.Tensor | None = None,
+                  scatter: int = SCATTER_AUTO, stream=None) -> torch.Tensor:
+    """values := sum_e scatter(K_e) through the CRAC arrays (asynchronous)."""
+    values = _numeric_args(p, ke, values)
+    _lib.check(_lib.load().assemble_crac(p.handle, _ptr(ke), _ptr(values), scatter,
+                                         _stream(stream)), "assemble_crac")
+    return values
+
+
+def reassemble_values(p: Pattern, fmt: int, ke: torch.Tensor, values: torch.Tensor | None = None,
+                      scatter: int = SCATTER_AUTO, stream=None) -> torch.Tensor:
+    """Value-only re-assembly on an existing pattern (asynchronous)."""
+    values = _numeric_args(p, ke, values)
+    _lib.check(_lib.load().reassemble_values(p.handle, fmt, _ptr(ke), _ptr(values), scatter,
+                                             _stream(stream)), "reassemble_values")
+    return values
+
+
+def load():
+    """Load the native library (raises if it is not built)."""
+    return _lib.load()

@@ -1,0 +1,90 @@
+"""ctypes declarations of libfeasm.so (the C ABI in include/feasm.h).
+
+Loading fails loudly when the library has not been built: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libfeasm.so")
+
+FEASM_OK = 0
+STATUS_NAMES = {
+    0: "FEASM_OK",
+    -1: "FEASM_EINVAL",
+    -2: "FEASM_ERANGE",
+    -3: "FEASM_ENOMEM",
+    -4: "FEASM_EHIP",
+    -5: "FEASM_EOVERFLOW",
+    -6: "FEASM_ELIMIT",
+}
+
+# Every function the header declares, with (restype, argtypes).
+P = ctypes.c_void_p
+I32 = ctypes.c_int32
+I64 = ctypes.c_int64
+U32 = ctypes.c_uint32
+INT = ctypes.c_int
+PP = ctypes.POINTER(ctypes.c_void_p)
+PI64 = ctypes.POINTER(ctypes.c_int64)
+PI32 = ctypes.POINTER(ctypes.c_int32)
+
+SIGNATURES = {
+    "pattern_build": (INT, [P, I64, I32, I32, I64, U32, P, PP]),
+    "assemble_csr": (INT, [P, P, P, INT, P]),
+    "assemble_crac": (INT, [P, P, P, INT, P]),
+    "reassemble_values": (INT, [P, INT, P, P, INT, P]),
+    "pattern_info": (INT, [P, PI64, PI64, PI64, PI32]),
+    "pattern_arrays": (INT, [P, PP, PP, PP, PP]),
+    "pattern_colouring": (INT, [P, PP, PP, PP]),
+    "pattern_free": (None, [P]),
+    "last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load():
+    """Load libfeasm.so (raises ImportError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2012_00585_amd.build` "
+            "(the HIP library is required; there is no fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class FeasmError(RuntimeError):
+    def __init__(self, what, code):
+        msg = load().last_error().decode(errors="replace")
+        super().__init__(f"{what} failed with {STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def check(code, what):
+    if code != FEASM_OK:
+        raise FeasmError(what, code)
+
+
+_hip = None
+
+
+def hip():
+    """The HIP runtime (for device-to-device copies of borrowed arrays)."""
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpyAsync.restype = INT
+        _hip.hipMemcpyAsync.argtypes = [P, P, ctypes.c_size_t, INT, P]
+    return _hip

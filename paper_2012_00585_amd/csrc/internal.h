@@ -1,0 +1,108 @@
+// Internal declarations of libfeasm (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "feasm.h"
+
+namespace feasm {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+
+struct Status {
+    int code = FEASM_OK;
+    bool ok() const { return code == FEASM_OK; }
+};
+
+#define FEASM_FAIL(code_, msg_)                 \
+    do {                                        \
+        ::feasm::set_error(msg_);               \
+        return (code_);                         \
+    } while (0)
+
+#define FEASM_HIP(call_)                                                              \
+    do {                                                                              \
+        hipError_t e__ = (call_);                                                     \
+        if (e__ != hipSuccess) {                                                      \
+            ::feasm::set_error(std::string(#call_) + ": " + hipGetErrorString(e__)); \
+            return (e__ == hipErrorOutOfMemory ? FEASM_ENOMEM : FEASM_EHIP);          \
+        }                                                                             \
+    } while (0)
+
+// ---------------------------------------------------------------- handle
+struct OffsetCache;  // value-only re-assembly lookup cache (assemble.hip)
+
+}  // namespace feasm
+
+struct feasm_pattern {
+    int device = 0;
+    int64_t n_elem = 0;
+    int32_t k = 0, d = 0, n = 0;
+    int64_t n_nodes = 0, n_rows = 0;
+    uint32_t flags = 0;
+    bool has_repeats = false;  // some element lists a node twice
+
+    int32_t* conn = nullptr;  // dev [n_elem*k]
+
+    // node-level pattern: node v couples with node_col[node_ptr[v] .. node_ptr[v+1])
+    int64_t node_nnz = 0, node_runs = 0;
+    int64_t* node_ptr = nullptr;     // dev [n_nodes+1]
+    int32_t* node_col = nullptr;     // dev [node_nnz]
+    int32_t* node_nruns = nullptr;   // dev [n_nodes]
+    int64_t* noderun_ptr = nullptr;  // dev [n_nodes+1]
+
+    // node -> incident (element*k + local) entries
+    int64_t* inc_ptr = nullptr;  // dev [n_nodes+1]
+    int32_t* inc_q = nullptr;    // dev [n_elem*k]
+
+    // CSR
+    int64_t nnz = 0;
+    int32_t* row_ptr = nullptr;  // dev [n_rows+1]
+    int32_t* col_idx = nullptr;  // dev [nnz]
+
+    // CRAC
+    int64_t n_ca = 0;
+    int32_t* crac_row_ptr = nullptr;  // dev [n_rows+1]
+    int32_t* ca = nullptr;            // dev [n_ca]
+
+    // colouring
+    int32_t n_colours = 0;
+    std::vector<int64_t> colour_ptr;  // host [n_colours+1]
+    int32_t* colour_elems = nullptr;  // dev [n_elem]
+    int32_t* elem_colour = nullptr;   // dev [n_elem]
+
+    feasm::OffsetCache* cache = nullptr;
+};
+
+namespace feasm {
+
+// ---------------------------------------------------------------- helpers
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Exclusive scan: out[i] = sum_{j<i} in[j] for i in [0, n]; out[n] is the total.
+// `scratch` must hold scan_scratch_elems(n) int64 values.
+int64_t scan_scratch_elems(int64_t n);
+template <typename T>
+int exclusive_scan(const T* in, int64_t n, int64_t* out, int64_t* scratch, hipStream_t s);
+
+// Colouring (colour.hip): fills p->elem_colour, colour_elems, colour_ptr, n_colours.
+int build_colouring(feasm_pattern* p, hipStream_t s);
+
+// Free every device array of the handle.
+void release_pattern(feasm_pattern* p);
+void release_cache(feasm_pattern* p);
+
+// XCD-aware block order: hardware dispatches workgroup b to XCD b % 8.
+// Maps it to a logical index so that each XCD processes one contiguous range.
+__device__ inline int64_t xcd_block(int64_t b, int64_t nb) {
+    const int64_t x = b % 8, q = nb / 8, rem = nb % 8;
+    const int64_t start = x * q + (x < rem ? x : rem);
+    return start + b / 8;
+}
+
+}  // namespace feasm

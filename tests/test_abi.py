@@ -1,0 +1,91 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared
+symbol, and rejects bad arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "feasm.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "defined")))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2012_00585_amd import _lib
+
+    return _lib.load()
+
+
+def test_header_declares_the_four_calls():
+    names = _declared_functions()
+    for f in ("pattern_build", "assemble_csr", "assemble_crac", "reassemble_values"):
+        assert f in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2012_00585_amd import _lib
+
+    names = _declared_functions()
+    assert set(names) == set(_lib.SIGNATURES), (names, sorted(_lib.SIGNATURES))
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def _build(lib, conn, E, k, d, nn, flags):
+    h = ctypes.c_void_p()
+    rc = lib.pattern_build(conn, E, k, d, nn, flags, None, ctypes.byref(h))
+    return rc, h
+
+
+def test_pattern_build_rejects_bad_arguments(lib):
+    from paper_2012_00585_amd._lib import STATUS_NAMES
+
+    dummy = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    cases = [
+        ((None, 4, 4, 1, 9, 1), "FEASM_EINVAL"),
+        ((dummy, 0, 4, 1, 9, 1), "FEASM_EINVAL"),
+        ((dummy, 4, 0, 1, 9, 1), "FEASM_EINVAL"),
+        ((dummy, 4, 4, 0, 9, 1), "FEASM_EINVAL"),
+        ((dummy, 4, 4, 1, 0, 1), "FEASM_EINVAL"),
+        ((dummy, 4, 4, 1, 9, 0), "FEASM_EINVAL"),      # neither CSR nor CRAC
+        ((dummy, 4, 4, 1, 9, 64), "FEASM_EINVAL"),     # unknown flag
+        ((dummy, 2 ** 30, 4, 1, 9, 1), "FEASM_EOVERFLOW"),
+        ((dummy, 4, 4, 3, 2 ** 30, 1), "FEASM_EOVERFLOW"),
+        ((dummy, 4, 100, 50, 9, 1), "FEASM_ELIMIT"),
+    ]
+    for args, want in cases:
+        rc, h = _build(lib, *args)
+        assert STATUS_NAMES[rc] == want, (args, rc)
+        assert not h.value
+        assert lib.last_error()
+    h = ctypes.c_void_p()
+    assert lib.pattern_build(dummy, 4, 4, 1, 9, 1, None, None) == -1
+
+
+def test_numeric_calls_reject_null_handle(lib):
+    d = ctypes.c_void_p(0x1000)
+    assert lib.assemble_csr(None, d, d, 0, None) == -1
+    assert b"null handle" in lib.last_error()
+    assert lib.assemble_crac(None, d, d, 0, None) == -1
+    assert lib.reassemble_values(None, 0, d, d, 0, None) == -1
+    assert lib.pattern_info(None, None, None, None, None) == -1
+    assert lib.pattern_arrays(None, None, None, None, None) == -1
+    assert lib.pattern_colouring(None, None, None, None) == -1
+    lib.pattern_free(None)  # ignored
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_2012_00585_amd import _lib
+
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(ImportError):
+        _lib.load()

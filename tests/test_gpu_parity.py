@@ -1,0 +1,255 @@
+"""Parity of the HIP path with the serial oracle (GPU).
+
+Patterns (row_ptr, col_idx, CRAC pairs) must be bit-exact.  Values must meet
+|g - o| <= 1e-12 * A per entry (A = sum of |contributions|, from the oracle);
+small-integer element matrices, whose sums are exact in any order, must match
+bit for bit.  Every case runs CSR and CRAC, atomic and coloured, assembly and
+value-only re-assembly (first call records lookups, second reuses them).
+"""
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from fe_inputs import configs, matrices, meshes
+from tests._checks import assert_values_close
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def feasm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2012_00585_amd as f
+
+    f.load()
+    return f
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def run_device(feasm, conn, d, nn, ke, flags=None, strategies=None):
+    """Pattern + every numeric variant on the device; returns numpy results."""
+    flags = flags or (feasm.BUILD_CSR | feasm.BUILD_CRAC | feasm.BUILD_COLOUR)
+    dev = torch.device("cuda:0")
+    conn_d = torch.from_numpy(np.ascontiguousarray(conn, dtype=np.int32)).to(dev)
+    p = feasm.pattern_build(conn_d, d, nn, flags)
+    out = {"p": p, "nnz": p.nnz, "n_ca": p.n_ca, "n_colours": p.n_colours}
+    out["row_ptr"], out["col_idx"] = (_np(t) for t in p.csr())
+    out["crac_row_ptr"], out["ca"] = (_np(t) for t in p.crac())
+    cptr, celems, ecol = p.colouring()
+    out["colour_ptr"], out["colour_elems"], out["elem_colour"] = cptr, _np(celems), _np(ecol)
+    ke_d = torch.from_numpy(np.ascontiguousarray(ke)).to(dev)
+    strategies = strategies or [(fmt, sc) for fmt in ("csr", "crac")
+                                for sc in (feasm.SCATTER_ATOMIC, feasm.SCATTER_COLOURED)]
+    vals = {}
+    for fmt, sc in strategies:
+        fn = feasm.assemble_csr if fmt == "csr" else feasm.assemble_crac
+        fcode = feasm.FMT_CSR if fmt == "csr" else feasm.FMT_CRAC
+        vals[(fmt, sc, "assemble")] = _np(fn(p, ke_d, scatter=sc))
+        vals[(fmt, sc, "reassemble1")] = _np(feasm.reassemble_values(p, fcode, ke_d, scatter=sc))
+        vals[(fmt, sc, "reassemble2")] = _np(feasm.reassemble_values(p, fcode, ke_d, scatter=sc))
+    torch.cuda.synchronize()
+    out["values"] = vals
+    return out
+
+
+def check_against_oracle(orc, conn, d, nn, ke, res, exact=False):
+    rp, ci = orc.pattern(conn, d, nn)
+    crp, ca = orc.crac(rp, ci, d * nn)
+    assert res["nnz"] == rp[-1]
+    assert (res["row_ptr"] == rp).all()
+    assert (res["col_idx"] == ci).all()
+    assert res["n_ca"] == ca.size
+    assert (res["crac_row_ptr"] == crp).all()
+    assert (res["ca"] == ca).all()
+    # colouring: valid, and the grouped list is a permutation sorted within colours
+    nc = res["n_colours"]
+    assert orc.colouring_valid(conn, nn, res["elem_colour"], nc)
+    ptr = res["colour_ptr"]
+    assert ptr[0] == 0 and ptr[-1] == conn.shape[0]
+    ce = res["colour_elems"]
+    assert (np.sort(ce) == np.arange(conn.shape[0])).all()
+    for c in range(nc):
+        seg = ce[ptr[c]:ptr[c + 1]]
+        assert (res["elem_colour"][seg] == c).all()
+        assert (np.diff(seg) > 0).all()
+    ov, oa = orc.assemble(conn, d, ke, rp, ci)
+    for key, v in res["values"].items():
+        if exact:
+            assert (v == ov).all(), key
+        else:
+            assert_values_close(v, ov, oa, what=str(key))
+
+
+def _fan(n_tri):
+    """Triangles (centre, i, i+1) around node 0: node 0 has n_tri elements."""
+    i = np.arange(n_tri)
+    conn = np.stack([np.zeros_like(i), 1 + i, 1 + (i + 1) % n_tri], axis=1)
+    return conn.astype(np.int32), n_tri + 1
+
+
+def _repeated():
+    conn, nn = meshes.quad_mesh(3)
+    conn = conn.copy()
+    conn[4, 2] = conn[4, 0]  # element 4 lists a node twice (degenerate quad)
+    return conn, nn
+
+
+CASES = [
+    ("one_quad", lambda: meshes.quad_mesh(1), 1),
+    ("quad3x5_d2", lambda: meshes.quad_mesh(3, 5), 2),
+    ("hex2_d3", lambda: meshes.hex_mesh(2), 3),
+    ("hex5x3x2_d1", lambda: meshes.hex_mesh(5, 3, 2), 1),
+    ("hex7_d3", lambda: meshes.hex_mesh(7), 3),
+    ("tet2perm_d3", lambda: meshes.tet10_mesh(2, perm_seed=0), 3),
+    ("tet3perm_d2", lambda: meshes.tet10_mesh(3, perm_seed=5), 2),
+    ("q3quad3_d2", lambda: meshes.qp_quad_mesh(3, 3), 2),
+    ("q8quad2_d1", lambda: meshes.qp_quad_mesh(2, 8), 1),
+    ("q4quad2_d4", lambda: meshes.qp_quad_mesh(2, 4), 4),
+    ("fan400_bignode", lambda: _fan(400), 1),
+    ("repeated_node", _repeated, 2),
+    ("unused_nodes", lambda: (meshes.quad_mesh(4)[0], 40), 1),
+]
+
+
+@pytest.mark.parametrize("name,make,d", CASES, ids=[c[0] for c in CASES])
+def test_small_cases_spd(feasm, orc, name, make, d):
+    conn, nn = make()
+    E, k = conn.shape
+    say(f"[parity] {name}: E={E} k={k} d={d} nodes={nn}")
+    ke = matrices.ke_spd(E, k * d, seed=3)
+    res = run_device(feasm, conn, d, nn, ke)
+    check_against_oracle(orc, conn, d, nn, ke, res)
+    res["p"].free()
+
+
+@pytest.mark.parametrize("name,make,d", CASES[:8] + CASES[10:], ids=[c[0] for c in CASES[:8] + CASES[10:]])
+def test_small_cases_integer_exact(feasm, orc, name, make, d):
+    conn, nn = make()
+    E, k = conn.shape
+    say(f"[exact] {name}: E={E} k={k} d={d}")
+    ke = matrices.ke_small_int(E, k * d, seed=9)
+    res = run_device(feasm, conn, d, nn, ke)
+    check_against_oracle(orc, conn, d, nn, ke, res, exact=True)
+    res["p"].free()
+
+
+def test_quad64_workload(feasm, orc):
+    w = configs.quad64()
+    say("[parity] quad64 (64x64 Q1, d=1, zero-row-sum Ke)")
+    ke = w.ke()
+    res = run_device(feasm, w.conn, w.dofs_per_node, w.n_nodes, ke)
+    assert res["nnz"] == 37249 and res["n_ca"] == 25092
+    assert res["n_colours"] >= 4
+    check_against_oracle(orc, w.conn, w.dofs_per_node, w.n_nodes, ke, res)
+    res["p"].free()
+
+
+def test_all_ones_dummy_element_bit_exact(feasm, orc):
+    # The paper's dummy element (all ones): sums are exact small integers.
+    conn, nn = meshes.hex_mesh(16)
+    d = 3
+    E, k = conn.shape
+    say("[exact] hex16 all-ones")
+    ke = matrices.ke_ones(E, k * d)
+    res = run_device(feasm, conn, d, nn, ke)
+    check_against_oracle(orc, conn, d, nn, ke, res, exact=True)
+    for v in res["values"].values():
+        assert v.sum() == E * (k * d) ** 2
+    res["p"].free()
+
+
+@pytest.fixture(scope="module")
+def hex64(feasm):
+    w = configs.hex64()
+    say("[hex64] generating Ke (262144 x 24 x 24)")
+    return w, w.ke()
+
+
+def test_hex64_pattern_and_values(feasm, orc, hex64):
+    w, ke = hex64
+    say("[parity] hex64 full size: pattern, CSR/CRAC atomic/coloured")
+    res = run_device(feasm, w.conn, 3, w.n_nodes, ke, strategies=[
+        ("csr", feasm.SCATTER_ATOMIC), ("crac", feasm.SCATTER_ATOMIC),
+        ("crac", feasm.SCATTER_COLOURED)])
+    assert res["nnz"] == 64701513 and res["n_ca"] == 14527112
+    check_against_oracle(orc, w.conn, 3, w.n_nodes, ke, res)
+    res["p"].free()
+
+
+def _sha(a):
+    return hashlib.sha256(np.asarray(a, dtype=np.int64).tobytes()).hexdigest()
+
+
+def test_tet40_pattern_and_sampled_values(feasm, orc):
+    g = json.load(open(os.path.join(GOLDEN, "tet40_counts.json")))
+    w = configs.tet40()
+    say("[parity] tet40 (permuted tet10): generating Ke (384000 x 30 x 30)")
+    ke = w.ke()
+    dev = torch.device("cuda:0")
+    p = feasm.pattern_build(torch.from_numpy(w.conn).to(dev), 3, w.n_nodes,
+                            feasm.BUILD_CSR | feasm.BUILD_CRAC | feasm.BUILD_COLOUR)
+    assert (p.nnz, p.n_ca) == (g["nnz"], g["n_ca"])
+    rp, ci = (_np(t) for t in p.csr())
+    crp, ca = (_np(t) for t in p.crac())
+    assert _sha(rp) == g["row_ptr_sha_int64"]
+    assert _sha(ci) == g["col_idx_sha_int64"]
+    assert _sha(ca) == g["ca_sha_int64"]
+    ke_d = torch.from_numpy(ke).to(dev)
+    rows = np.random.default_rng(0).choice(p.n_rows, size=3000, replace=False)
+    ref = orc.rows(w.conn, 3, w.n_nodes, ke, rows)
+    for fmt, sc in (("csr", feasm.SCATTER_ATOMIC), ("crac", feasm.SCATTER_ATOMIC),
+                    ("csr", feasm.SCATTER_COLOURED), ("crac", feasm.SCATTER_COLOURED)):
+        fn = feasm.assemble_csr if fmt == "csr" else feasm.assemble_crac
+        v = _np(fn(p, ke_d, scatter=sc))
+        g_all, o_all, a_all = [], [], []
+        for i, (cols, ov, oa) in zip(rows, ref):
+            assert (ci[rp[i]:rp[i + 1]] == cols).all()
+            g_all.append(v[rp[i]:rp[i + 1]])
+            o_all.append(ov)
+            a_all.append(oa)
+        assert_values_close(np.concatenate(g_all), np.concatenate(o_all), np.concatenate(a_all),
+                            what=f"tet40 {fmt} {sc}")
+        # sum of all entries equals the sum of all element entries
+        assert abs(v.sum() - ke.sum()) <= 1e-12 * np.abs(ke).sum()
+    p.free()
+
+
+def test_error_paths_on_device(feasm):
+    dev = torch.device("cuda:0")
+    conn, nn = meshes.quad_mesh(3)
+    bad = conn.copy()
+    bad[5, 1] = nn + 7
+    with pytest.raises(feasm.FeasmError, match="ERANGE"):
+        feasm.pattern_build(torch.from_numpy(bad).to(dev), 1, nn)
+    bad[5, 1] = -1
+    with pytest.raises(feasm.FeasmError, match="element 5, local node 1"):
+        feasm.pattern_build(torch.from_numpy(bad).to(dev), 1, nn)
+    conn_f, nn_f = _fan(3000)  # node 0: 9000 candidate entries > 8192
+    with pytest.raises(feasm.FeasmError, match="ELIMIT"):
+        feasm.pattern_build(torch.from_numpy(conn_f).to(dev), 1, nn_f)
+    # a handle without colouring rejects the coloured strategy
+    p = feasm.pattern_build(torch.from_numpy(conn).to(dev), 1, nn, feasm.BUILD_CSR)
+    ke = torch.zeros(conn.shape[0] * 16, dtype=torch.float64, device=dev)
+    with pytest.raises(feasm.FeasmError, match="colour"):
+        feasm.assemble_csr(p, ke, scatter=feasm.SCATTER_COLOURED)
+    with pytest.raises(feasm.FeasmError, match="without CRAC"):
+        feasm.assemble_crac(p, ke)
+    with pytest.raises(ValueError):
+        feasm.assemble_csr(p, ke[:-1])
+    p.free()
