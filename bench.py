@@ -117,6 +117,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="hex64", choices=["hex64", "quad64", "tet40"])
     ap.add_argument("--cpu-reps", type=int, default=3, help="0 skips the oracle baseline")
+    ap.add_argument("--only", default="", help="comma-separated variants to time (default: all)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -163,6 +164,9 @@ def main():
     }
     reps = max(args.steps, 5)
     variants = {}
+    if args.only:
+        keep = set(args.only.split(","))
+        full = {k: v for k, v in full.items() if k in keep}
     for name, fn in full.items():
         log(f"[bench] variant {name}")
         t_full = stats(time_calls(fn, reps, args.warmup))
