@@ -65,9 +65,12 @@ enum { FEASM_FMT_CSR = 0, FEASM_FMT_CRAC = 1 };
 
 /* scatter strategy of the numeric calls */
 enum {
-    FEASM_SCATTER_AUTO = 0,     /* the library's choice for this handle */
+    FEASM_SCATTER_AUTO = 0,     /* the library's choice for this handle (row-owned) */
     FEASM_SCATTER_ATOMIC = 1,   /* one hardware FP64 atomic add per contribution */
     FEASM_SCATTER_COLOURED = 2, /* one launch per colour, plain read-modify-write */
+    FEASM_SCATTER_OWNER = 3,    /* row-owned: each node row is summed by one wavefront
+                                   from the incident elements, in element order, and
+                                   written once (no atomics, no reset pass) */
     FEASM_ACCUMULATE = 0x100    /* or-ed into `scatter`: add into `values` without
                                    resetting it first (values += sum_e scatter(K_e)) */
 };

@@ -26,6 +26,7 @@ FMT_CRAC = 1
 SCATTER_AUTO = 0
 SCATTER_ATOMIC = 1
 SCATTER_COLOURED = 2
+SCATTER_OWNER = 3
 ACCUMULATE = 0x100  # or into `scatter`: add into values without resetting them
 
 _HIP_D2D = 3  # hipMemcpyDeviceToDevice

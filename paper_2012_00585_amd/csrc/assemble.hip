@@ -207,6 +207,252 @@ __global__ void k_zero(double* __restrict__ p, int64_t n) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Row-owned assembly.  The paper's fastest CPU methods give each global row
+// to one thread at a time (a spin lock held in the row pointer, Section 3.2)
+// and add whole contiguous slices of K's rows into it (Section 3.3).  On the
+// GPU the same exclusivity comes from static ownership instead of a lock: a
+// group of G lanes owns node v, i.e. the d DOF rows d*v .. d*v+d-1, whose
+// values are one contiguous block.  It walks the incident (element, local
+// node a) entries in increasing element order, looks up where each of the
+// element's nodes sits in row d*v (binary search of the CSR columns, or the
+// linear block search over the CRAC pairs, both staged in LDS), and adds
+// rows d*a .. d*a+d-1 of K_e into an LDS accumulator.  The block is written
+// once with coalesced stores: no atomics, no reset pass, and every value is
+// the sum of its contributions in increasing element order -- the order of
+// the sequential listing.
+struct OwnArgs {
+    const int32_t* conn;
+    int32_t k, d, n;
+    const int64_t* inc_ptr;
+    const int32_t* inc_q;
+    const int32_t* row_ptr;
+    const int32_t* col_idx;
+    const int32_t* crac_row_ptr;
+    const int32_t* ca;
+    const double* ke;
+    double* values;
+    int64_t n_nodes;
+    int32_t acc_doubles;  // per group: d*d*max_deg
+    int32_t idx_ints;     // per group: CSR d*max_deg, CRAC 2*max_deg+2
+    int32_t group_bytes;  // per group LDS bytes (8-byte multiple)
+    int32_t accumulate;
+};
+
+template <int FMT>
+__device__ inline int32_t row_lookup(const int32_t* sidx, int32_t ncols, int32_t npairs, int32_t rs,
+                                     int32_t col) {
+    if (FMT == kCSR) {
+        int32_t lo = 0, hi = ncols;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (sidx[mid] < col)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        return (lo < ncols && sidx[lo] == col) ? lo : -1;
+    } else {
+        if (npairs == 0) return -1;
+        int32_t q = 0;
+        while (q + 1 < npairs && sidx[2 * q + 2] <= col) ++q;
+        const int32_t first = sidx[2 * q], vpos = sidx[2 * q + 1], vend = sidx[2 * q + 3];
+        if (col < first || col >= first + (vend - vpos)) return -1;
+        return vpos + (col - first) - rs;
+    }
+}
+
+template <int FMT, int G, int J, int B, bool REPEATS>
+__global__ void __launch_bounds__(64) k_owner(OwnArgs A) {
+    extern __shared__ double lds_d[];
+    __shared__ int32_t s_lmax;
+    constexpr int NG = 64 / G;
+    const int g = threadIdx.x / G, l = threadIdx.x % G;
+    const int64_t v = xcd_block(blockIdx.x, gridDim.x) * NG + g;
+    const bool active = v < A.n_nodes;
+    const int32_t k = A.k, d = A.d, n = A.n, dn = d * n;
+    double* acc = reinterpret_cast<double*>(reinterpret_cast<char*>(lds_d) + g * A.group_bytes);
+    int32_t* sidx = reinterpret_cast<int32_t*>(acc + A.acc_doubles);
+    int32_t* scol = sidx + A.idx_ints;
+
+    if (threadIdx.x == 0) s_lmax = 0;
+    int32_t rs = 0, ncols = 0, npairs = 0;
+    int64_t ib = 0, L = 0;
+    if (active) {
+        const int32_t R = d * (int32_t)v;
+        ib = A.inc_ptr[v];
+        L = A.inc_ptr[v + 1] - ib;
+        if (FMT == kCSR) {
+            rs = A.row_ptr[R];
+            ncols = A.row_ptr[R + 1] - rs;
+            for (int x = l; x < ncols; x += G) sidx[x] = A.col_idx[rs + x];
+        } else {
+            const int32_t pb = A.crac_row_ptr[R], pe = A.crac_row_ptr[R + 1];
+            npairs = (pe - pb) >> 1;
+            if (npairs > 0) {
+                for (int x = l; x < pe - pb + 2; x += G) sidx[x] = A.ca[pb + x];
+                rs = A.ca[pb + 1];
+                ncols = A.ca[pe + 1] - rs;
+            }
+        }
+        for (int x = l; x < d * ncols; x += G) acc[x] = 0.0;
+    }
+    __syncthreads();
+    if (active && l == 0) atomicMax(&s_lmax, (int32_t)L);
+    // this lane's slab entries j = l + u*G: K row offset c1 and column s
+    int jc1[J], jb[J], jc[J];
+#pragma unroll
+    for (int u = 0; u < J; ++u) {
+        const int j = l + u * G;
+        const int c1 = j / n, s = j - (j / n) * n;
+        jc1[u] = c1;
+        jb[u] = s / d;
+        jc[u] = s - (s / d) * d;
+    }
+    __syncthreads();
+    const int32_t lmax = s_lmax;
+    for (int32_t t0 = 0; t0 < lmax; t0 += B) {
+        double val[B][J];
+        if (active) {
+            // where each node of the batch's elements sits in row d*v
+            for (int w = l; w < B * k; w += G) {
+                const int tb = w / k, b = w - (w / k) * k;
+                if (t0 + tb < L) {
+                    const int32_t q = A.inc_q[ib + t0 + tb];
+                    const int32_t col = d * A.conn[(int64_t)(q / k) * k + b];
+                    scol[w] = row_lookup<FMT>(sidx, ncols, npairs, rs, col);
+                }
+            }
+            // rows d*a .. d*a+d-1 of each element matrix (contiguous)
+#pragma unroll
+            for (int tb = 0; tb < B; ++tb) {
+                if (t0 + tb < L) {
+                    const int32_t q = A.inc_q[ib + t0 + tb];
+                    const int64_t e = q / k, a = q - e * k;
+                    const double* slab = A.ke + e * (int64_t)n * n + a * d * n;
+#pragma unroll
+                    for (int u = 0; u < J; ++u) {
+                        const int j = l + u * G;
+                        val[tb][u] = j < dn ? __builtin_nontemporal_load(slab + j) : 0.0;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int tb = 0; tb < B; ++tb) {
+            if (active && t0 + tb < L) {
+#pragma unroll
+                for (int u = 0; u < J; ++u) {
+                    const int j = l + u * G;
+                    if (j < dn) {
+                        const int32_t off = scol[tb * k + jb[u]];
+                        if (off >= 0) {
+                            double* dst = acc + jc1[u] * ncols + off + jc[u];
+                            if (REPEATS)
+                                atomicAdd(dst, val[tb][u]);
+                            else
+                                *dst += val[tb][u];
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (active) {
+        double* out = A.values + rs;
+        if (A.accumulate)
+            for (int x = l; x < d * ncols; x += G) out[x] += acc[x];
+        else
+            for (int x = l; x < d * ncols; x += G) out[x] = acc[x];
+    }
+}
+
+struct OwnShape {
+    int g, j, b;
+    int32_t group_bytes;
+};
+
+// Lanes per node row G, slab values per lane J, incidences per batch B; G
+// grows (fewer node rows per 64-lane block) until the per-row LDS fits.
+// Returns g = 0 if even one row per block does not fit in 64 KiB.
+OwnShape owner_shape(const feasm_pattern* p, int fmt) {
+    const int dn = p->d * p->n;
+    int g = 4;
+    while (g < dn && g < 64) g <<= 1;
+    for (;; g <<= 1) {
+        if (g > 64) return {0, 0, 0, 0};
+        const int j = (int)ceil_div(dn, g);
+        const int jj = j <= 1 ? 1 : j <= 2 ? 2 : j <= 4 ? 4 : j <= 8 ? 8 : 16;
+        const int b = jj <= 2 ? 8 : jj == 4 ? 4 : jj == 8 ? 2 : 1;
+        const int64_t idx = (fmt == kCSR) ? (int64_t)p->d * p->max_deg : 2 * (int64_t)p->max_deg + 2;
+        const int64_t bytes = (int64_t)p->d * p->d * p->max_deg * 8 + idx * 4 + (int64_t)b * p->k * 4;
+        const int64_t gb = ceil_div(bytes, 8) * 8;
+        if (gb * (64 / g) <= 64 * 1024) return {g, jj, b, (int32_t)gb};
+    }
+}
+
+template <int FMT, int G, int J, int B>
+int launch_owner_t(const feasm_pattern* p, OwnArgs& A, hipStream_t s) {
+    constexpr int NG = 64 / G;
+    const int64_t blocks = ceil_div(p->n_nodes, NG);
+    const size_t lds = (size_t)A.group_bytes * NG;
+    if (p->has_repeats)
+        k_owner<FMT, G, J, B, true><<<(unsigned)blocks, 64, lds, s>>>(A);
+    else
+        k_owner<FMT, G, J, B, false><<<(unsigned)blocks, 64, lds, s>>>(A);
+    FEASM_HIP(hipGetLastError());
+    return FEASM_OK;
+}
+
+template <int FMT>
+int launch_owner_f(const feasm_pattern* p, OwnArgs& A, hipStream_t s) {
+    const OwnShape sh = owner_shape(p, FMT);
+    if (sh.g == 0)
+        FEASM_FAIL(FEASM_ELIMIT, "row-owned assembly: node rows too long for the LDS accumulator");
+    A.idx_ints = (FMT == kCSR) ? p->d * p->max_deg : 2 * p->max_deg + 2;
+    A.acc_doubles = p->d * p->d * p->max_deg;
+    A.group_bytes = sh.group_bytes;
+    switch (sh.g * 100 + sh.j) {
+        case 401: return launch_owner_t<FMT, 4, 1, 8>(p, A, s);
+        case 801: return launch_owner_t<FMT, 8, 1, 8>(p, A, s);
+        case 1601: return launch_owner_t<FMT, 16, 1, 8>(p, A, s);
+        case 3201: return launch_owner_t<FMT, 32, 1, 8>(p, A, s);
+        case 6401: return launch_owner_t<FMT, 64, 1, 8>(p, A, s);
+        case 6402: return launch_owner_t<FMT, 64, 2, 8>(p, A, s);
+        case 6404: return launch_owner_t<FMT, 64, 4, 4>(p, A, s);
+        case 6408: return launch_owner_t<FMT, 64, 8, 2>(p, A, s);
+        default: return launch_owner_t<FMT, 64, 16, 1>(p, A, s);
+    }
+}
+
+bool owner_fits(const feasm_pattern* p, int fmt) {
+    return (int64_t)p->d * p->n <= 1024 && owner_shape(p, fmt).g != 0;
+}
+
+int launch_owner(const feasm_pattern* p, int fmt, const double* ke, double* values, bool accumulate,
+                 hipStream_t s) {
+    if ((int64_t)p->d * p->n > 1024)
+        FEASM_FAIL(FEASM_ELIMIT, "row-owned assembly supports d * n <= 1024");
+    OwnArgs A{};
+    A.conn = p->conn;
+    A.k = p->k;
+    A.d = p->d;
+    A.n = p->n;
+    A.inc_ptr = p->inc_ptr;
+    A.inc_q = p->inc_q;
+    A.row_ptr = p->row_ptr;
+    A.col_idx = p->col_idx;
+    A.crac_row_ptr = p->crac_row_ptr;
+    A.ca = p->ca;
+    A.ke = ke;
+    A.values = values;
+    A.n_nodes = p->n_nodes;
+    A.accumulate = accumulate ? 1 : 0;
+    return fmt == kCSR ? launch_owner_f<kCSR>(p, A, s) : launch_owner_f<kCRAC>(p, A, s);
+}
+
 // Threads per element and values per thread, by element-matrix size.
 struct Shape {
     int tpe, u;
@@ -254,9 +500,12 @@ int assemble_impl(const feasm_pattern* p, int fmt, const double* ke, double* val
         FEASM_FAIL(FEASM_EINVAL, std::string(who) + ": handle was built without CRAC");
     const bool accumulate = (scatter & FEASM_ACCUMULATE) != 0;
     scatter &= ~FEASM_ACCUMULATE;
-    if (scatter == FEASM_SCATTER_AUTO) scatter = FEASM_SCATTER_ATOMIC;
-    if (scatter != FEASM_SCATTER_ATOMIC && scatter != FEASM_SCATTER_COLOURED)
+    if (scatter == FEASM_SCATTER_AUTO)
+        scatter = owner_fits(p, fmt) ? FEASM_SCATTER_OWNER : FEASM_SCATTER_ATOMIC;
+    if (scatter != FEASM_SCATTER_ATOMIC && scatter != FEASM_SCATTER_COLOURED &&
+        scatter != FEASM_SCATTER_OWNER)
         FEASM_FAIL(FEASM_EINVAL, std::string(who) + ": unknown scatter strategy");
+    if (scatter == FEASM_SCATTER_OWNER) return launch_owner(p, fmt, ke, values, accumulate, s);
     if (scatter == FEASM_SCATTER_COLOURED && !(p->flags & FEASM_BUILD_COLOUR))
         FEASM_FAIL(FEASM_EINVAL,
                    std::string(who) + ": coloured scatter needs a handle built with colouring");

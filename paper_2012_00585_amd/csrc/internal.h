@@ -46,6 +46,8 @@ struct feasm_pattern {
     int64_t n_nodes = 0, n_rows = 0;
     uint32_t flags = 0;
     bool has_repeats = false;  // some element lists a node twice
+    int32_t max_deg = 0;       // most neighbour nodes of any node
+    int32_t max_inc = 0;       // most incident (element, local node) entries of any node
 
     int32_t* conn = nullptr;  // dev [n_elem*k]
 
@@ -56,7 +58,7 @@ struct feasm_pattern {
     int32_t* node_nruns = nullptr;   // dev [n_nodes]
     int64_t* noderun_ptr = nullptr;  // dev [n_nodes+1]
 
-    // node -> incident (element*k + local) entries
+    // node -> incident (element*k + local) entries, ascending within a node
     int64_t* inc_ptr = nullptr;  // dev [n_nodes+1]
     int32_t* inc_q = nullptr;    // dev [n_elem*k]
 

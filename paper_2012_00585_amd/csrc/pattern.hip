@@ -30,6 +30,8 @@ struct BuildStatus {
     int32_t big_count;             // nodes whose candidate list overflows the wave path
     int32_t limit_hit;             // a node exceeds the large-node path too
     int32_t repeats;               // some element lists a node twice
+    int32_t max_deg;               // largest number of neighbour nodes of a node
+    int32_t max_inc;               // largest number of incident (element, local) entries
 };
 
 constexpr int kSmallBlock = 64;    // one wavefront per node
@@ -83,6 +85,53 @@ __device__ inline uint64_t lanes_below() {
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
+// Ascending bitonic sort of keys[0, M) (M a power of two) by a whole block.
+template <int BLOCK>
+__device__ inline void block_bitonic_sort(int32_t* keys, int M) {
+    const int tid = threadIdx.x;
+    for (int size = 2; size <= M; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = tid; t < (M >> 1); t += BLOCK) {
+                const int lo = 2 * t - (t & (stride - 1));
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const int32_t x = keys[lo], y = keys[hi];
+                if ((x > y) == up) {
+                    keys[lo] = y;
+                    keys[hi] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Sorts each node's incidence list (entries e*k + a) ascending, so that
+// element order is fixed whatever order the atomic fill produced.  Same node
+// split as k_node_rows: lists whose candidate count exceeds CAP of the
+// wavefront path are done by the large-node path.
+template <int BLOCK, int CAP>
+__global__ void __launch_bounds__(BLOCK)
+    k_sort_incidence(int32_t k, const int64_t* __restrict__ inc_ptr, int32_t* __restrict__ inc_q,
+                     int64_t n_nodes, const int32_t* __restrict__ list,
+                     const int32_t* __restrict__ list_len) {
+    __shared__ int32_t keys[CAP];
+    const int64_t count = list ? (int64_t)*list_len : n_nodes;
+    for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
+        const int64_t v = list ? list[i] : i;
+        const int64_t b = inc_ptr[v];
+        const int64_t L = inc_ptr[v + 1] - b;
+        if (L * k > CAP || L < 2) continue;
+        int M = 1;
+        while (M < L) M <<= 1;
+        for (int t = threadIdx.x; t < M; t += BLOCK) keys[t] = t < L ? inc_q[b + t] : INT_MAX;
+        __syncthreads();
+        block_bitonic_sort<BLOCK>(keys, M);
+        for (int t = threadIdx.x; t < L; t += BLOCK) inc_q[b + t] = keys[t];
+        __syncthreads();
+    }
+}
+
 // Per node v: sorted unique neighbour nodes.  COUNT pass writes degree and
 // number of runs; FILL pass writes the list at node_ptr[v].  Nodes are taken
 // from `list` (length *list_len) if given, else all of [0, n_nodes).
@@ -124,22 +173,7 @@ __global__ void __launch_bounds__(BLOCK)
             keys[t] = key;
         }
         __syncthreads();
-        // bitonic sort of keys[0, M), ascending
-        for (int size = 2; size <= M; size <<= 1) {
-            for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                for (int t = tid; t < (M >> 1); t += BLOCK) {
-                    const int lo = 2 * t - (t & (stride - 1));
-                    const int hi = lo + stride;
-                    const bool up = (lo & size) == 0;
-                    const int32_t x = keys[lo], y = keys[hi];
-                    if ((x > y) == up) {
-                        keys[lo] = y;
-                        keys[hi] = x;
-                    }
-                }
-                __syncthreads();
-            }
-        }
+        block_bitonic_sort<BLOCK>(keys, M);
         // unique entries and run starts, compacted in order
         int64_t n_unique = 0, n_run = 0;
         for (int base = 0; base < C; base += BLOCK) {
@@ -172,6 +206,8 @@ __global__ void __launch_bounds__(BLOCK)
         if (!FILL && tid == 0) {
             deg[v] = (int32_t)n_unique;
             nruns[v] = (int32_t)n_run;
+            atomicMax(&st->max_deg, (int32_t)n_unique);
+            atomicMax(&st->max_inc, (int32_t)(C / k));
         }
         __syncthreads();
     }
@@ -290,7 +326,7 @@ int build(feasm_pattern* p, const int32_t* conn_in, hipStream_t s) {
 
     BuildStatus* st;
     TRY(tmp.alloc((char**)&st, sizeof(BuildStatus)));
-    BuildStatus st0{ULLONG_MAX, 0, 0, 0};
+    BuildStatus st0{ULLONG_MAX, 0, 0, 0, 0, 0};
     FEASM_HIP(hipMemcpyAsync(st, &st0, sizeof(st0), hipMemcpyHostToDevice, s));
 
     // 1. incidence
@@ -349,6 +385,8 @@ int build(feasm_pattern* p, const int32_t* conn_in, hipStream_t s) {
                                  "candidate neighbour list exceeds " +
                                      std::to_string(kBigCap) + " entries");
     p->has_repeats = hst.repeats != 0;
+    p->max_deg = hst.max_deg;
+    p->max_inc = hst.max_inc;
     p->node_nnz = totals[0];
     p->node_runs = totals[1];
     p->nnz = d * d * p->node_nnz;
@@ -367,6 +405,11 @@ int build(feasm_pattern* p, const int32_t* conn_in, hipStream_t s) {
     k_node_rows<kBigBlock, kBigCap, true><<<256, kBigBlock, 0, s>>>(
         p->conn, (int32_t)k, p->inc_ptr, p->inc_q, nn, big_list, &st->big_count, nullptr,
         nullptr, p->node_ptr, p->node_col, nullptr, st);
+    FEASM_HIP(hipGetLastError());
+    k_sort_incidence<kSmallBlock, kSmallCap><<<grid_for(nn, 1, 1 << 20), kSmallBlock, 0, s>>>(
+        (int32_t)k, p->inc_ptr, p->inc_q, nn, nullptr, nullptr);
+    k_sort_incidence<kBigBlock, kBigCap><<<256, kBigBlock, 0, s>>>(
+        (int32_t)k, p->inc_ptr, p->inc_q, nn, big_list, &st->big_count);
     FEASM_HIP(hipGetLastError());
 
     // 5. DOF-level arrays

@@ -55,7 +55,8 @@ def run_device(feasm, conn, d, nn, ke, flags=None, strategies=None):
     out["colour_ptr"], out["colour_elems"], out["elem_colour"] = cptr, _np(celems), _np(ecol)
     ke_d = torch.from_numpy(np.ascontiguousarray(ke)).to(dev)
     strategies = strategies or [(fmt, sc) for fmt in ("csr", "crac")
-                                for sc in (feasm.SCATTER_ATOMIC, feasm.SCATTER_COLOURED)]
+                                for sc in (feasm.SCATTER_ATOMIC, feasm.SCATTER_COLOURED,
+                                           feasm.SCATTER_OWNER)]
     vals = {}
     for fmt, sc in strategies:
         fn = feasm.assemble_csr if fmt == "csr" else feasm.assemble_crac
@@ -68,7 +69,13 @@ def run_device(feasm, conn, d, nn, ke, flags=None, strategies=None):
     return out
 
 
-def check_against_oracle(orc, conn, d, nn, ke, res, exact=False):
+OWNER = 3  # FEASM_SCATTER_OWNER
+
+
+def check_against_oracle(orc, conn, d, nn, ke, res, exact=False, owner_exact=True):
+    """owner_exact: the row-owned strategy sums every entry in increasing
+    element order, the sequential listing's order, so without repeated nodes
+    its values equal the oracle's bit for bit."""
     rp, ci = orc.pattern(conn, d, nn)
     crp, ca = orc.crac(rp, ci, d * nn)
     assert res["nnz"] == rp[-1]
@@ -90,7 +97,7 @@ def check_against_oracle(orc, conn, d, nn, ke, res, exact=False):
         assert (np.diff(seg) > 0).all()
     ov, oa = orc.assemble(conn, d, ke, rp, ci)
     for key, v in res["values"].items():
-        if exact:
+        if exact or (owner_exact and key[1] == OWNER):
             assert (v == ov).all(), key
         else:
             assert_values_close(v, ov, oa, what=str(key))
@@ -134,7 +141,7 @@ def test_small_cases_spd(feasm, orc, name, make, d):
     say(f"[parity] {name}: E={E} k={k} d={d} nodes={nn}")
     ke = matrices.ke_spd(E, k * d, seed=3)
     res = run_device(feasm, conn, d, nn, ke)
-    check_against_oracle(orc, conn, d, nn, ke, res)
+    check_against_oracle(orc, conn, d, nn, ke, res, owner_exact=(name != "repeated_node"))
     res["p"].free()
 
 
@@ -186,7 +193,8 @@ def test_hex64_pattern_and_values(feasm, orc, hex64):
     say("[parity] hex64 full size: pattern, CSR/CRAC atomic/coloured")
     res = run_device(feasm, w.conn, 3, w.n_nodes, ke, strategies=[
         ("csr", feasm.SCATTER_ATOMIC), ("crac", feasm.SCATTER_ATOMIC),
-        ("crac", feasm.SCATTER_COLOURED)])
+        ("crac", feasm.SCATTER_COLOURED), ("csr", feasm.SCATTER_OWNER),
+        ("crac", feasm.SCATTER_OWNER)])
     assert res["nnz"] == 64701513 and res["n_ca"] == 14527112
     check_against_oracle(orc, w.conn, 3, w.n_nodes, ke, res)
     res["p"].free()
@@ -214,7 +222,8 @@ def test_tet40_pattern_and_sampled_values(feasm, orc):
     rows = np.random.default_rng(0).choice(p.n_rows, size=3000, replace=False)
     ref = orc.rows(w.conn, 3, w.n_nodes, ke, rows)
     for fmt, sc in (("csr", feasm.SCATTER_ATOMIC), ("crac", feasm.SCATTER_ATOMIC),
-                    ("csr", feasm.SCATTER_COLOURED), ("crac", feasm.SCATTER_COLOURED)):
+                    ("csr", feasm.SCATTER_COLOURED), ("crac", feasm.SCATTER_COLOURED),
+                    ("csr", feasm.SCATTER_OWNER), ("crac", feasm.SCATTER_OWNER)):
         fn = feasm.assemble_csr if fmt == "csr" else feasm.assemble_crac
         v = _np(fn(p, ke_d, scatter=sc))
         g_all, o_all, a_all = [], [], []
@@ -223,8 +232,10 @@ def test_tet40_pattern_and_sampled_values(feasm, orc):
             g_all.append(v[rp[i]:rp[i + 1]])
             o_all.append(ov)
             a_all.append(oa)
-        assert_values_close(np.concatenate(g_all), np.concatenate(o_all), np.concatenate(a_all),
-                            what=f"tet40 {fmt} {sc}")
+        g_all, o_all = np.concatenate(g_all), np.concatenate(o_all)
+        assert_values_close(g_all, o_all, np.concatenate(a_all), what=f"tet40 {fmt} {sc}")
+        if sc == feasm.SCATTER_OWNER:
+            assert (g_all == o_all).all()
         # sum of all entries equals the sum of all element entries
         assert abs(v.sum() - ke.sum()) <= 1e-12 * np.abs(ke).sum()
     p.free()
@@ -252,4 +263,35 @@ def test_error_paths_on_device(feasm):
         feasm.assemble_crac(p, ke)
     with pytest.raises(ValueError):
         feasm.assemble_csr(p, ke[:-1])
+    p.free()
+
+
+def test_accumulate_adds_without_reset(feasm, orc):
+    conn, nn = meshes.hex_mesh(3)
+    d = 2
+    E, k = conn.shape
+    ke = matrices.ke_small_int(E, k * d, seed=2)
+    dev = torch.device("cuda:0")
+    p = feasm.pattern_build(torch.from_numpy(conn).to(dev), d, nn,
+                            feasm.BUILD_CSR | feasm.BUILD_CRAC | feasm.BUILD_COLOUR)
+    rp, ci = orc.pattern(conn, d, nn)
+    ov, _ = orc.assemble(conn, d, ke, rp, ci)
+    ke_d = torch.from_numpy(ke).to(dev)
+    for sc in (feasm.SCATTER_ATOMIC, feasm.SCATTER_COLOURED, feasm.SCATTER_OWNER):
+        for fn in (feasm.assemble_csr, feasm.assemble_crac):
+            base = torch.full((p.nnz,), 3.0, dtype=torch.float64, device=dev)
+            v = _np(fn(p, ke_d, base, sc | feasm.ACCUMULATE))
+            assert (v == ov + 3.0).all(), (fn.__name__, sc)
+    p.free()
+
+
+def test_owner_is_deterministic(feasm):
+    w = configs.tet40(m=12)
+    dev = torch.device("cuda:0")
+    ke = torch.from_numpy(w.ke()).to(dev)
+    p = feasm.pattern_build(torch.from_numpy(w.conn).to(dev), 3, w.n_nodes)
+    a = feasm.assemble_crac(p, ke, scatter=feasm.SCATTER_OWNER).clone()
+    b = feasm.assemble_csr(p, ke, scatter=feasm.SCATTER_OWNER)
+    c = feasm.reassemble_values(p, feasm.FMT_CRAC, ke)
+    assert torch.equal(a, b) and torch.equal(a, c)
     p.free()
