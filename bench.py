@@ -129,6 +129,9 @@ def main():
     ap.add_argument("--workload", default="hex64", choices=["hex64", "quad64", "tet40"])
     ap.add_argument("--cpu-reps", type=int, default=3, help="0 skips the oracle baseline")
     ap.add_argument("--only", default="", help="comma-separated variants to time (default: all)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run 3 plain device copies of this many MiB (a known-size "
+                         "reference for hardware byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -142,6 +145,15 @@ def main():
 
     feasm.load()
     dev = torch.device("cuda:0")
+    if args.copy_mib > 0:
+        n = args.copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copied {args.copy_mib} MiB three times (counter reference)")
+        del src, dst
     w, wdesc = workload(args.workload)
     log(f"[bench] {wdesc}: generating element matrices")
     ke = w.ke()
@@ -224,6 +236,15 @@ def main():
     kernel_ms = v["scatter_only_ms"]["mean"]
     spec_bytes = algorithmic_bytes(w, p, fmt, "atomic")
     achieved = v["algorithmic_bytes"] / (kernel_ms * 1e-3) / 1e9
+    # HBM traffic measured by rocprofv3 counters for this variant and workload,
+    # valid only while the kernel sources are those the counters were taken on
+    from paper_2012_00585_amd import rocprof_summary
+
+    prof = os.path.join(ROOT, "profiles", f"{best}_{args.workload}.md")
+    tbytes, thash = rocprof_summary.read_traffic(prof)
+    traffic = None
+    if tbytes is not None and thash == rocprof_summary.source_hash():
+        traffic = tbytes
     line = {
         "metric": METRIC,
         "value": w.n_elem / (ms_per_step * 1e-3),
@@ -244,7 +265,8 @@ def main():
         "effective_GBps_note": ("scatter-method bytes (Ke + conn + index arrays + values "
                                 "read and write) over the step time"),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_source": os.path.relpath(prof, ROOT) if traffic else None,
                      "kernel": (f"k_owner ({best}, one launch)" if strategy == "owner" else
                                 f"k_assemble ({best}, scatter only)"),
                      "bytes_per_launch": v["algorithmic_bytes"],

@@ -170,6 +170,29 @@ int pattern_arrays(const feasm_pattern* p, const int32_t** row_ptr, const int32_
 int pattern_colouring(const feasm_pattern* p, const int64_t** colour_ptr,
                       const int32_t** colour_elems, const int32_t** element_colour);
 
+/*
+ * Launch-shape tuning of one handle (used by the autotuner; 0 restores the
+ * library default).  Results do not depend on these settings.
+ *   FEASM_TUNE_OWNER_BLOCKS_PER_CU  row-owned strategy: 0 = one 64-lane block
+ *                                   per node-row tile; n > 0 = a persistent
+ *                                   grid of n blocks per compute unit
+ *   FEASM_TUNE_THREADS_PER_ELEM     atomic/coloured strategies: lanes per
+ *                                   element, one of 16, 32, 64, 128, 256
+ *   FEASM_TUNE_OWNER_ROWS           row-owned strategy with elements of more
+ *                                   than 64 entries per node row: node rows per
+ *                                   wavefront, 1, 2 or 4
+ *   FEASM_TUNE_OWNER_BATCH          row-owned strategy: element rows loaded per
+ *                                   batch, 8 or 16
+ * Returns EINVAL for an unknown key or value.
+ */
+enum {
+    FEASM_TUNE_OWNER_BLOCKS_PER_CU = 1,
+    FEASM_TUNE_THREADS_PER_ELEM = 2,
+    FEASM_TUNE_OWNER_ROWS = 3,
+    FEASM_TUNE_OWNER_BATCH = 4
+};
+int pattern_tune(feasm_pattern* p, int key, int64_t value);
+
 /* Releases the handle and its device arrays (synchronises the device). NULL is ignored. */
 void pattern_free(feasm_pattern* p);
 

@@ -29,6 +29,11 @@ SCATTER_COLOURED = 2
 SCATTER_OWNER = 3
 ACCUMULATE = 0x100  # or into `scatter`: add into values without resetting them
 
+TUNE_OWNER_BLOCKS_PER_CU = 1
+TUNE_THREADS_PER_ELEM = 2
+TUNE_OWNER_ROWS = 3
+TUNE_OWNER_BATCH = 4
+
 _HIP_D2D = 3  # hipMemcpyDeviceToDevice
 
 
@@ -120,6 +125,10 @@ class Pattern:
         ptr = [cp[i] for i in range(self.n_colours + 1)]
         return (ptr, self._copy(ce, self.n_elem, torch.int32, stream),
                 self._copy(ec, self.n_elem, torch.int32, stream))
+
+    def tune(self, key: int, value: int):
+        """Set a launch-shape knob of this handle (0 = library default)."""
+        _lib.check(_lib.load().pattern_tune(self.handle, key, value), "pattern_tune")
 
     def free(self):
         if self._h is not None:

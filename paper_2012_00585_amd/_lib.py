@@ -40,6 +40,7 @@ SIGNATURES = {
     "pattern_info": (INT, [P, PI64, PI64, PI64, PI32]),
     "pattern_arrays": (INT, [P, PP, PP, PP, PP]),
     "pattern_colouring": (INT, [P, PP, PP, PP]),
+    "pattern_tune": (INT, [P, INT, I64]),
     "pattern_free": (None, [P]),
     "last_error": (ctypes.c_char_p, []),
 }

@@ -36,7 +36,7 @@ __device__ inline uint64_t priority(uint32_t e) {
 }
 
 __global__ void k_jp_round(const int32_t* __restrict__ conn, int32_t k, int64_t n_elem,
-                           const int64_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc_q,
+                           const int64_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc_elem,
                            int32_t* __restrict__ colour, int32_t* __restrict__ stamp, int32_t round,
                            int32_t* __restrict__ remaining, int32_t* __restrict__ max_colour) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_elem;
@@ -47,7 +47,7 @@ __global__ void k_jp_round(const int32_t* __restrict__ conn, int32_t k, int64_t 
         for (int32_t a = 0; a < k && ready; ++a) {
             const int32_t v = conn[e * k + a];
             for (int64_t t = inc_ptr[v]; t < inc_ptr[v + 1]; ++t) {
-                const int32_t f = inc_q[t] / k;
+                const int32_t f = inc_elem[t];
                 if (f == e) continue;
                 if (stamp[f] >= round && priority((uint32_t)f) > mine) {
                     ready = false;
@@ -67,7 +67,7 @@ __global__ void k_jp_round(const int32_t* __restrict__ conn, int32_t k, int64_t 
             for (int32_t a = 0; a < k; ++a) {
                 const int32_t v = conn[e * k + a];
                 for (int64_t t = inc_ptr[v]; t < inc_ptr[v + 1]; ++t) {
-                    const int32_t f = inc_q[t] / k;
+                    const int32_t f = inc_elem[t];
                     if (f == e || stamp[f] >= round) continue;
                     const int32_t c = colour[f] - base;
                     if (c >= 0 && c < 64) used |= 1ull << c;
@@ -169,7 +169,7 @@ int build_colouring(feasm_pattern* p, hipStream_t s) {
         constexpr int kBatch = 4;
         for (int r = 0; r < kBatch; ++r, ++round) {
             k_fill_i32<<<1, 64, 0, s>>>(counters, 1, 0);
-            k_jp_round<<<grid(E, 256), 256, 0, s>>>(p->conn, p->k, E, p->inc_ptr, p->inc_q,
+            k_jp_round<<<grid(E, 256), 256, 0, s>>>(p->conn, p->k, E, p->inc_ptr, p->inc_elem,
                                                     p->elem_colour, stamp, round, counters,
                                                     counters + 1);
         }

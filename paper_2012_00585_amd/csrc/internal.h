@@ -60,7 +60,9 @@ struct feasm_pattern {
 
     // node -> incident (element*k + local) entries, ascending within a node
     int64_t* inc_ptr = nullptr;  // dev [n_nodes+1]
-    int32_t* inc_q = nullptr;    // dev [n_elem*k]
+    int32_t* inc_q = nullptr;      // dev [n_elem*k] entries e*k + a
+    int32_t* inc_elem = nullptr;   // dev [n_elem*k] element e of each entry (after build)
+    int32_t* inc_local = nullptr;  // dev [n_elem*k] local node a of each entry
 
     // CSR
     int64_t nnz = 0;
@@ -79,12 +81,18 @@ struct feasm_pattern {
     int32_t* elem_colour = nullptr;   // dev [n_elem]
 
     feasm::OffsetCache* cache = nullptr;
+
+    // tuning (0 = library default)
+    int32_t tune_owner_blocks_per_cu = 0;  // >0: persistent row-owned grid of this size per CU
+    int32_t tune_atomic_tpe = 0;           // threads per element of the atomic/coloured scatter
+    int32_t tune_owner_rows = 0;           // >1: node rows per wavefront (row-owned, large elements)
+    int32_t tune_owner_batch = 0;          // incidence entries loaded per batch (8 or 16)
 };
 
 namespace feasm {
 
 // ---------------------------------------------------------------- helpers
-inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Exclusive scan: out[i] = sum_{j<i} in[j] for i in [0, n]; out[n] is the total.
 // `scratch` must hold scan_scratch_elems(n) int64 values.

@@ -132,6 +132,17 @@ __global__ void __launch_bounds__(BLOCK)
     }
 }
 
+// Splits sorted entries e*k + a into element and local-node arrays.
+__global__ void k_split_incidence(int64_t ek, int32_t k, const int32_t* __restrict__ inc,
+                                  int32_t* __restrict__ elem, int32_t* __restrict__ local) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ek;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t q = inc[t];
+        elem[t] = q / k;
+        local[t] = q - (q / k) * k;
+    }
+}
+
 // Per node v: sorted unique neighbour nodes.  COUNT pass writes degree and
 // number of runs; FILL pass writes the list at node_ptr[v].  Nodes are taken
 // from `list` (length *list_len) if given, else all of [0, n_nodes).
@@ -410,6 +421,10 @@ int build(feasm_pattern* p, const int32_t* conn_in, hipStream_t s) {
         (int32_t)k, p->inc_ptr, p->inc_q, nn, nullptr, nullptr);
     k_sort_incidence<kBigBlock, kBigCap><<<256, kBigBlock, 0, s>>>(
         (int32_t)k, p->inc_ptr, p->inc_q, nn, big_list, &st->big_count);
+    TRY(dalloc(&p->inc_local, ek));
+    TRY(dalloc(&p->inc_elem, ek));
+    k_split_incidence<<<grid_for(ek, 256), 256, 0, s>>>(ek, (int32_t)k, p->inc_q, p->inc_elem,
+                                                        p->inc_local);
     FEASM_HIP(hipGetLastError());
 
     // 5. DOF-level arrays
@@ -440,7 +455,8 @@ int build(feasm_pattern* p, const int32_t* conn_in, hipStream_t s) {
 
 void release_pattern(feasm_pattern* p) {
     void* arrs[] = {p->conn,    p->node_ptr,     p->node_col, p->node_nruns, p->noderun_ptr,
-                    p->inc_ptr, p->inc_q,        p->row_ptr,  p->col_idx,    p->crac_row_ptr,
+                    p->inc_ptr, p->inc_q,        p->inc_elem, p->inc_local,
+                    p->row_ptr,  p->col_idx,    p->crac_row_ptr,
                     p->ca,      p->colour_elems, p->elem_colour};
     for (void* a : arrs)
         if (a) (void)hipFree(a);

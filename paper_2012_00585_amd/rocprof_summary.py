@@ -1,0 +1,154 @@
+"""Summaries of rocprofv3 runs of the library's kernels.
+
+rocprofv3 writes a SQLite ("rocpd") database per run.  This module reads
+
+* a ``--kernel-trace`` database: per-kernel dispatch count and duration;
+* ``--pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE`` databases: per-dispatch HBM
+  read and write counters (KiB).  Each counter is scaled by what it reads for
+  a plain device copy of known size found in the same run (bench.py's
+  ``--copy-mib``), so the bytes are real bytes.
+
+and writes a short markdown summary with the numbers and the commands that
+produced them.  ``source_hash()`` fingerprints the HIP sources, so a reader
+can tell whether a summary still describes the current kernels.
+
+    python -m paper_2012_00585_amd.rocprof_summary --trace T.db --fetch F.db \
+        --write W.db --kernel k_owner_rows --copy-mib 1024 --workload hex64 \
+        --command "..." --out profiles/k_owner_rows_hex64.md
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import glob
+import hashlib
+import os
+import re
+import sqlite3
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(PKG, "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def kernel_durations(db):
+    """{kernel name: [durations in us]} from a kernel-trace database."""
+    c = sqlite3.connect(db)
+    out = collections.defaultdict(list)
+    for name, start, end in c.execute("select name, start, end from kernels"):
+        out[name].append((end - start) / 1e3)
+    return dict(out)
+
+
+def counter_values(db, counter):
+    """{kernel name: [per-dispatch values]} of one counter."""
+    c = sqlite3.connect(db)
+    out = collections.defaultdict(list)
+    for name, cn, val in c.execute(
+            "select kernel_name, counter_name, value from counters_collection"):
+        if cn == counter:
+            out[name].append(float(val))
+    return dict(out)
+
+
+def _match(d, pattern):
+    keys = [k for k in d if re.search(pattern, k)]
+    return keys
+
+
+def copy_factor(values, copy_mib):
+    """Bytes per counter unit, from the largest copyBuffer dispatch of copy_mib MiB."""
+    keys = _match(values, r"copyBuffer|copy")
+    best = 0.0
+    for k in keys:
+        best = max(best, max(values[k]))
+    if best <= 0:
+        return None
+    return copy_mib * (1 << 20) / best
+
+
+def summarize(trace, fetch, write, kernel, copy_mib, workload, command, algorithmic_bytes=None):
+    durs = kernel_durations(trace)
+    names = _match(durs, kernel)
+    if not names:
+        raise SystemExit(f"kernel {kernel!r} not in trace; have {sorted(durs)[:8]}")
+    lines = [f"# {kernel} on {workload}", ""]
+    lines.append(f"source hash: {source_hash()}")
+    lines.append("")
+    lines.append("Commands (run from the repository root on the GPU host):")
+    lines.append("")
+    for c in command:
+        lines.append(f"    {c}")
+    lines.append("")
+    lines.append("| kernel | dispatches | mean us | min us |")
+    lines.append("|---|---|---|---|")
+    for nme in sorted(names, key=lambda x: -len(durs[x])):
+        v = durs[nme]
+        lines.append(f"| {nme[:100]} | {len(v)} | {sum(v) / len(v):.2f} | {min(v):.2f} |")
+    lines.append("")
+    fv = counter_values(fetch, "FETCH_SIZE") if fetch else {}
+    wv = counter_values(write, "WRITE_SIZE") if write else {}
+    ff = copy_factor(fv, copy_mib) if fv else None
+    wf = copy_factor(wv, copy_mib) if wv else None
+    if fv and wv and ff and wf:
+        lines.append(f"Counter scale from a {copy_mib} MiB device copy: FETCH_SIZE x {ff:.1f} "
+                     f"bytes/unit, WRITE_SIZE x {wf:.1f} bytes/unit")
+        lines.append("")
+        lines.append("| kernel | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch | HBM bytes/dispatch |")
+        lines.append("|---|---|---|---|")
+        for nme in names:
+            f = fv.get(nme, [])
+            w = wv.get(nme, [])
+            if not f or not w:
+                continue
+            fa, wa = sum(f) / len(f), sum(w) / len(w)
+            tb = fa * ff + wa * wf
+            lines.append(f"| {nme[:100]} | {fa:.1f} | {wa:.1f} | {tb:.0f} |")
+            lines.append("")
+            lines.append(f"traffic_bytes_per_launch: {tb:.0f}")
+            if algorithmic_bytes:
+                lines.append(f"algorithmic_bytes_per_launch: {algorithmic_bytes}")
+                lines.append(f"traffic_over_algorithmic: {tb / algorithmic_bytes:.3f}")
+    lines.append("")
+    return "\n".join(lines)
+
+
+def read_traffic(path):
+    """(traffic bytes per launch, source hash) from a summary, or (None, None)."""
+    if not os.path.exists(path):
+        return None, None
+    text = open(path).read()
+    m = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    h = re.search(r"source hash: (\w+)", text)
+    return (int(m.group(1)) if m else None), (h.group(1) if h else None)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--kernel", required=True, help="regular expression of the kernel name")
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--workload", default="hex64")
+    ap.add_argument("--command", action="append", default=[])
+    ap.add_argument("--algorithmic-bytes", type=int)
+    ap.add_argument("--out")
+    a = ap.parse_args()
+    text = summarize(a.trace, a.fetch, a.write, a.kernel, a.copy_mib, a.workload, a.command,
+                     a.algorithmic_bytes)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(text)
+    print(text)
+
+
+if __name__ == "__main__":
+    main()

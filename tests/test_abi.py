@@ -79,6 +79,7 @@ def test_numeric_calls_reject_null_handle(lib):
     assert lib.pattern_info(None, None, None, None, None) == -1
     assert lib.pattern_arrays(None, None, None, None, None) == -1
     assert lib.pattern_colouring(None, None, None, None) == -1
+    assert lib.pattern_tune(None, 1, 0) == -1
     lib.pattern_free(None)  # ignored
 
 

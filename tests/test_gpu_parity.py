@@ -295,3 +295,51 @@ def test_owner_is_deterministic(feasm):
     c = feasm.reassemble_values(p, feasm.FMT_CRAC, ke)
     assert torch.equal(a, b) and torch.equal(a, c)
     p.free()
+
+
+@pytest.mark.parametrize("rows,batch", [(1, 8), (2, 8), (2, 16), (4, 8), (4, 16)])
+@pytest.mark.parametrize("mesh", ["hex7_d3", "tet3perm_d3", "q8quad2_d1"])
+def test_owner_launch_shapes_bit_exact(feasm, orc, mesh, rows, batch):
+    make = {"hex7_d3": (lambda: meshes.hex_mesh(7), 3),
+            "tet3perm_d3": (lambda: meshes.tet10_mesh(3, perm_seed=1), 3),
+            "q8quad2_d1": (lambda: meshes.qp_quad_mesh(2, 8), 1)}[mesh]
+    (conn, nn), d = make[0](), make[1]
+    E, k = conn.shape
+    say(f"[owner shapes] {mesh} rows={rows} batch={batch}")
+    ke = matrices.ke_spd(E, k * d, seed=6)
+    dev = torch.device("cuda:0")
+    p = feasm.pattern_build(torch.from_numpy(conn).to(dev), d, nn)
+    rp, ci = orc.pattern(conn, d, nn)
+    ov, _ = orc.assemble(conn, d, ke, rp, ci)
+    ke_d = torch.from_numpy(ke).to(dev)
+    for bpc in (0, 3):
+        p.tune(feasm.TUNE_OWNER_ROWS, rows)
+        p.tune(feasm.TUNE_OWNER_BATCH, batch)
+        p.tune(feasm.TUNE_OWNER_BLOCKS_PER_CU, bpc)
+        for fn in (feasm.assemble_csr, feasm.assemble_crac):
+            v = _np(fn(p, ke_d, scatter=feasm.SCATTER_OWNER))
+            assert (v == ov).all(), (fn.__name__, bpc)
+    p.free()
+
+
+def test_atomic_threads_per_element_tuning(feasm, orc):
+    conn, nn = meshes.hex_mesh(5)
+    d = 3
+    E, k = conn.shape
+    ke = matrices.ke_small_int(E, k * d, seed=1)
+    dev = torch.device("cuda:0")
+    p = feasm.pattern_build(torch.from_numpy(conn).to(dev), d, nn,
+                            feasm.BUILD_CSR | feasm.BUILD_CRAC | feasm.BUILD_COLOUR)
+    rp, ci = orc.pattern(conn, d, nn)
+    ov, _ = orc.assemble(conn, d, ke, rp, ci)
+    ke_d = torch.from_numpy(ke).to(dev)
+    for tpe in (64, 128, 256):
+        p.tune(feasm.TUNE_THREADS_PER_ELEM, tpe)
+        for sc in (feasm.SCATTER_ATOMIC, feasm.SCATTER_COLOURED):
+            for fn in (feasm.assemble_csr, feasm.assemble_crac):
+                assert (_np(fn(p, ke_d, scatter=sc)) == ov).all(), (tpe, sc)
+    with pytest.raises(feasm.FeasmError):
+        p.tune(feasm.TUNE_THREADS_PER_ELEM, 16)  # 576 entries need >= 36 lanes
+    with pytest.raises(feasm.FeasmError):
+        p.tune(99, 1)
+    p.free()
