@@ -183,18 +183,74 @@ int pattern_colouring(const feasm_pattern* p, const int64_t** colour_ptr,
  *                                   wavefront, 1, 2 or 4
  *   FEASM_TUNE_OWNER_BATCH          row-owned strategy: element rows loaded per
  *                                   batch, 8 or 16
+ *   FEASM_TUNE_STRATEGY             the strategy FEASM_SCATTER_AUTO resolves to
+ *                                   for this handle (and in batches)
  * Returns EINVAL for an unknown key or value.
  */
 enum {
     FEASM_TUNE_OWNER_BLOCKS_PER_CU = 1,
     FEASM_TUNE_THREADS_PER_ELEM = 2,
     FEASM_TUNE_OWNER_ROWS = 3,
-    FEASM_TUNE_OWNER_BATCH = 4
+    FEASM_TUNE_OWNER_BATCH = 4,
+    FEASM_TUNE_STRATEGY = 5
 };
 int pattern_tune(feasm_pattern* p, int key, int64_t value);
 
 /* Releases the handle and its device arrays (synchronises the device). NULL is ignored. */
 void pattern_free(feasm_pattern* p);
+
+/*
+ * Batched assembly: many independent meshes in one persistent launch.
+ *
+ * batch_create prepares the batch for `count` handles (host array; the
+ * handles must outlive the batch and all share `fmt`, FEASM_FMT_CSR or
+ * FEASM_FMT_CRAC).  Each mesh runs the strategy its handle's
+ * FEASM_TUNE_STRATEGY selects (AUTO = row-owned; row-owned meshes whose rows
+ * do not fit the LDS accumulator fall back to atomics) with its launch-shape
+ * knobs, except that element lanes are capped at 64.  `flags` may hold
+ * FEASM_ACCUMULATE (no reset).  The work of the whole batch -- counter reset,
+ * zero fill of the atomic and coloured meshes, one persistent launch per
+ * kernel path (and per colour for coloured meshes, chained) pulling work
+ * tiles from device counters -- is captured into one hipGraph.
+ * Synchronises the device.
+ *
+ * assemble_batch replays it on `stream`: ke[i] (dev double [n_elem_i][n][n])
+ * and values[i] (dev double [nnz_i]) are host arrays of device pointers; the
+ * values of every mesh are overwritten (or accumulated) exactly as
+ * assemble_<fmt> would.  When the pointer tables differ from the previous
+ * call they are uploaded first (and the host waits for that upload).  Calls
+ * on one batch must not overlap.
+ *
+ * With flags | FEASM_BATCH_PER_MESH_GRAPH the graph instead holds every
+ * mesh's own single-mesh kernels (largest first, on 4 parallel branches);
+ * it is recaptured whenever the pointer tables change.
+ *
+ * batch_info reports the number of phases, work tiles, persistent grid
+ * size and each mesh's kernel path (host array of `count` ints, may be NULL;
+ * zeros in per-mesh-graph mode).
+ */
+enum { FEASM_BATCH_PER_MESH_GRAPH = 0x200 };
+/*
+ * Workload generator (benchmarks and serving; not part of the assembly
+ * method): fills ke (dev double [n_elem][n][n]) with reproducible element
+ * matrices from counter-based Philox4x32-10 draws.  recipe 0: symmetric
+ * zero-row-sum ("laplacian", off-diagonals uniform in [-1, 1)); recipe 1:
+ * symmetric positive definite B B^T / n + I with unit-variance B.  Element
+ * e uses counter ((entry), e + elem_offset, recipe) under key `seed`, with
+ * exact or correctly rounded operations only, so any implementation of the
+ * same definition reproduces the bits.  Asynchronous; n*n*8 <= 64 KiB.
+ */
+int generate_ke(int recipe, int64_t n_elem, int32_t n, uint64_t seed, int64_t elem_offset,
+                double* ke, hipStream_t stream);
+
+typedef struct feasm_batch feasm_batch;
+int batch_create(const feasm_pattern* const* patterns, int64_t count, int fmt, uint32_t flags,
+                 feasm_batch** out);
+int assemble_batch(feasm_batch* b, const double* const* ke, double* const* values,
+                   hipStream_t stream);
+int batch_info(const feasm_batch* b, int32_t* n_phases, int64_t* n_tiles, int64_t* grid,
+               int32_t* paths);
+void batch_free(feasm_batch* b);
 
 /* Thread-local message describing the latest failed call on this thread. */
 const char* last_error(void);

@@ -33,6 +33,7 @@ TUNE_OWNER_BLOCKS_PER_CU = 1
 TUNE_THREADS_PER_ELEM = 2
 TUNE_OWNER_ROWS = 3
 TUNE_OWNER_BATCH = 4
+TUNE_STRATEGY = 5
 
 _HIP_D2D = 3  # hipMemcpyDeviceToDevice
 
@@ -196,6 +197,23 @@ def reassemble_values(p: Pattern, fmt: int, ke: torch.Tensor, values: torch.Tens
     _lib.check(_lib.load().reassemble_values(p.handle, fmt, _ptr(ke), _ptr(values), scatter,
                                              _stream(stream)), "reassemble_values")
     return values
+
+
+RECIPE_LAPLACIAN = 0
+RECIPE_SPD = 1
+
+
+def generate_ke(recipe: int, n_elem: int, n: int, seed: int, elem_offset: int = 0,
+                out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Reproducible element matrices on the device (workload generator)."""
+    if out is None:
+        out = torch.empty((n_elem, n, n), dtype=torch.float64, device="cuda")
+    _require(out, torch.float64, "out")
+    if out.numel() < n_elem * n * n:
+        raise ValueError("out too small")
+    _lib.check(_lib.load().generate_ke(recipe, n_elem, n, seed, elem_offset, _ptr(out),
+                                       _stream(stream)), "generate_ke")
+    return out
 
 
 def load():

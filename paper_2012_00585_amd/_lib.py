@@ -42,6 +42,11 @@ SIGNATURES = {
     "pattern_colouring": (INT, [P, PP, PP, PP]),
     "pattern_tune": (INT, [P, INT, I64]),
     "pattern_free": (None, [P]),
+    "generate_ke": (INT, [INT, I64, I32, ctypes.c_uint64, I64, P, P]),
+    "batch_create": (INT, [P, I64, INT, U32, PP]),
+    "assemble_batch": (INT, [P, P, P, P]),
+    "batch_info": (INT, [P, PI32, PI64, PI64, P]),
+    "batch_free": (None, [P]),
     "last_error": (ctypes.c_char_p, []),
 }
 

@@ -18,6 +18,9 @@ HIPCC_FLAGS = [
     "-fPIC",
     "-shared",
     "-munsafe-fp-atomics",
+    # no fused multiply-add contraction: FP64 results are exactly the written
+    # sequence of correctly rounded operations
+    "-ffp-contract=off",
     # keep the compiler from emitting packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",

@@ -1,0 +1,620 @@
+// Batched assembly: many independent meshes in one graph-captured launch.
+//
+// Every mesh keeps its own pattern handle, element matrices and values
+// array.  The host turns the batch into work tiles -- node-row tiles of
+// row-owned meshes, element blocks of atomic meshes, and one list per
+// colour for coloured meshes -- grouped by code path.  Each (phase, path)
+// group runs as one persistent kernel sized to the resident capacity of that
+// path, whose blocks pop chunks of tiles from a device counter (the same
+// device routines as the single-mesh kernels, so results are identical).
+// Path-specialised kernels keep each path's register budget, instead of one
+// kernel carrying the union of all paths.  Colours need a grid-wide order,
+// so colour phases are chained launches on a second graph branch that runs
+// beside the row-owned and atomic launches.  The whole sequence -- counter
+// reset, zero fill of the meshes that assemble with atomics or colours, the
+// launches -- is captured once into a hipGraph and replayed on the caller's
+// stream; a replay with new element-matrix or values pointers only refreshes
+// the device pointer table first.
+#include <algorithm>
+#include <array>
+#include <cstring>
+#include <utility>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+#include "scatter_device.h"
+
+struct feasm_batch;
+
+namespace feasm {
+namespace {
+
+using namespace scatter;
+
+// Kernel paths of the batch (one block of 64 lanes per tile).
+enum Path : int32_t {
+    kOwnG4 = 0, kOwnG8, kOwnG16, kOwnG32, kOwnG64J1, kOwnG64J2, kOwnG64J4, kOwnG64J8, kOwnG64J16,
+    kRows2J1, kRows2J2,
+    kElemA16, kElemA32, kElemA64, kElemP16, kElemP32, kElemP64,
+    kNumPaths
+};
+
+struct MeshDesc {
+    AsmArgs asm_args;   // element paths (ke/values/elem_list filled per tile)
+    OwnArgs own_args;   // row-owned paths (ke/values filled per tile)
+    const int64_t* colour_ptr;  // dev [n_colours+1]
+    int32_t path;
+};
+
+struct BatchTile {
+    int32_t mesh;
+    int32_t colour;  // colour list of element tiles of coloured meshes, else -1
+    int64_t index;   // logical block index within the mesh's path
+};
+
+struct ZeroChunk {
+    int32_t mesh;
+    int32_t pad;
+    int64_t first;
+    int64_t count;
+};
+
+constexpr int64_t kZeroChunk = 1 << 16;
+
+__global__ void __launch_bounds__(256)
+    k_batch_zero(const ZeroChunk* __restrict__ chunks, int64_t n_chunks, double* const* values) {
+    for (int64_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+        const ZeroChunk z = chunks[c];
+        double* p = values[z.mesh] + z.first;
+        for (int64_t i = threadIdx.x; i < z.count; i += blockDim.x) p[i] = 0.0;
+    }
+}
+
+__global__ void k_batch_reset(unsigned long long* counters, int32_t n) {
+    if ((int)threadIdx.x < n) counters[threadIdx.x] = 0ull;
+}
+
+// One persistent kernel per code path: blocks pop `chunk` tiles at a time
+// from the path's counter until the list is exhausted (every block leaves).
+template <int FMT, int PATH>
+__global__ void __launch_bounds__(64)
+    k_batch(const MeshDesc* __restrict__ meshes, const double* const* __restrict__ ke,
+            double* const* __restrict__ values, const BatchTile* __restrict__ tiles,
+            int64_t n_tiles, int64_t chunk, unsigned long long* counter) {
+    extern __shared__ double lds[];
+    __shared__ int64_t s_first;
+    for (;;) {
+        if (threadIdx.x == 0) s_first = (int64_t)atomicAdd(counter, (unsigned long long)chunk);
+        __syncthreads();
+        const int64_t first = s_first;
+        __syncthreads();
+        if (first >= n_tiles) break;
+        const int64_t last = first + chunk < n_tiles ? first + chunk : n_tiles;
+        for (int64_t t = first; t < last; ++t) {
+            const BatchTile T = tiles[t];
+            const MeshDesc* M = meshes + T.mesh;
+            if (PATH <= kRows2J2) {
+                OwnArgs A = M->own_args;
+                A.ke = ke[T.mesh];
+                A.values = values[T.mesh];
+                if (PATH == kOwnG4) owner_tiles<FMT, 4, 1, 8>(A, T.index, T.index + 1, lds);
+                if (PATH == kOwnG8) owner_tiles<FMT, 8, 1, 8>(A, T.index, T.index + 1, lds);
+                if (PATH == kOwnG16) owner_tiles<FMT, 16, 1, 8>(A, T.index, T.index + 1, lds);
+                if (PATH == kOwnG32) owner_tiles<FMT, 32, 1, 8>(A, T.index, T.index + 1, lds);
+                if (PATH == kOwnG64J1) owner_tiles<FMT, 64, 1, 8>(A, T.index, T.index + 1, lds);
+                if (PATH == kOwnG64J2) owner_tiles<FMT, 64, 2, 8>(A, T.index, T.index + 1, lds);
+                if (PATH == kOwnG64J4) owner_tiles<FMT, 64, 4, 4>(A, T.index, T.index + 1, lds);
+                if (PATH == kOwnG64J8) owner_tiles<FMT, 64, 8, 2>(A, T.index, T.index + 1, lds);
+                if (PATH == kOwnG64J16) owner_tiles<FMT, 64, 16, 1>(A, T.index, T.index + 1, lds);
+                if (PATH == kRows2J1) owner_rows_tile<FMT, 2, 1, 8>(A, T.index, lds);
+                if (PATH == kRows2J2) owner_rows_tile<FMT, 2, 2, 8>(A, T.index, lds);
+            } else {
+                AsmArgs A = M->asm_args;
+                A.ke = ke[T.mesh];
+                A.values = values[T.mesh];
+                if (T.colour >= 0) {
+                    const int64_t c0 = M->colour_ptr[T.colour], c1 = M->colour_ptr[T.colour + 1];
+                    A.elem_list = A.elem_list + c0;
+                    A.count = c1 - c0;
+                }
+                int32_t* li = reinterpret_cast<int32_t*>(lds);
+                if (PATH == kElemA16) elem_tile<FMT, true, 16, 1, 64>(A, T.index, li);
+                if (PATH == kElemA32) elem_tile<FMT, true, 32, 2, 64>(A, T.index, li);
+                if (PATH == kElemA64) elem_tile<FMT, true, 64, 16, 64>(A, T.index, li);
+                if (PATH == kElemP16) elem_tile<FMT, false, 16, 1, 64>(A, T.index, li);
+                if (PATH == kElemP32) elem_tile<FMT, false, 32, 2, 64>(A, T.index, li);
+                if (PATH == kElemP64) elem_tile<FMT, false, 64, 16, 64>(A, T.index, li);
+            }
+            __syncthreads();  // LDS is reused by the next tile
+        }
+    }
+}
+
+using BatchKernel = void (*)(const MeshDesc*, const double* const*, double* const*,
+                             const BatchTile*, int64_t, int64_t, unsigned long long*);
+
+template <int FMT, int... P>
+constexpr std::array<BatchKernel, sizeof...(P)> kernel_table(std::integer_sequence<int, P...>) {
+    return {&k_batch<FMT, P>...};
+}
+
+BatchKernel batch_kernel(int fmt, int path) {
+    static const auto t0 = kernel_table<0>(std::make_integer_sequence<int, kNumPaths>{});
+    static const auto t1 = kernel_table<1>(std::make_integer_sequence<int, kNumPaths>{});
+    return fmt == 0 ? t0[path] : t1[path];
+}
+
+}  // namespace
+}  // namespace feasm
+
+namespace feasm {
+namespace {
+
+// One persistent launch: the tiles of one code path in one phase (phase 0:
+// row-owned and atomic meshes; phase c+1: colour c of coloured meshes).
+struct Launch {
+    int32_t phase = 0;
+    int32_t path = 0;
+    BatchTile* d_tiles = nullptr;
+    int64_t n_tiles = 0;
+    size_t lds = 0;
+    int64_t grid = 0;
+    int64_t chunk = 1;
+    double work = 0;
+};
+
+}  // namespace
+}  // namespace feasm
+
+struct feasm_batch {
+    int fmt = 0;
+    int64_t count = 0;
+    int device = 0;
+    int accumulate = 0;
+    int per_mesh_graph = 0;  // mode: every mesh's own kernels in one graph
+    std::vector<const feasm_pattern*> patterns;
+    feasm::MeshDesc* d_meshes = nullptr;
+    std::vector<int64_t*> d_colour_ptrs;
+    std::vector<feasm::Launch> launches;
+    int32_t n_phases = 1;
+    unsigned long long* d_counters = nullptr;
+    feasm::ZeroChunk* d_zero = nullptr;
+    int64_t n_zero = 0;
+    const double** d_ke = nullptr;
+    double** d_values = nullptr;
+    std::vector<const double*> h_ke;  // last uploaded tables
+    std::vector<double*> h_values;
+    hipStream_t streams[3] = {nullptr, nullptr, nullptr};  // capture only
+    hipEvent_t events[3] = {nullptr, nullptr, nullptr};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<int32_t> paths;  // per mesh, for batch_info
+    static constexpr int kBranches = 4;
+    hipStream_t branch[kBranches] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t branch_done[kBranches] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+namespace feasm {
+namespace {
+
+// Path, per-block LDS bytes and tile granularity of one mesh given its tuning.
+int mesh_path(const feasm_pattern* p, int fmt, int strategy, MeshDesc& D, size_t& lds,
+              int64_t& per) {
+    const int64_t dn = (int64_t)p->d * p->n;
+    if (strategy == FEASM_SCATTER_OWNER) {
+        if (dn > 1024) FEASM_FAIL(FEASM_ELIMIT, "assemble_batch: row-owned path needs d*n <= 1024");
+        int g = 4;
+        while (g < dn && g < 64) g <<= 1;
+        for (;; g <<= 1) {
+            if (g > 64) FEASM_FAIL(FEASM_ELIMIT, "assemble_batch: node rows too long for LDS");
+            const int j = (int)ceil_div(dn, g);
+            const int jj = j <= 1 ? 1 : j <= 2 ? 2 : j <= 4 ? 4 : j <= 8 ? 8 : 16;
+            const int b = jj <= 2 ? 8 : jj == 4 ? 4 : jj == 8 ? 2 : 1;
+            const int64_t idx = (fmt == 0) ? (int64_t)p->d * p->max_deg : 2 * (int64_t)p->max_deg + 2;
+            const int64_t bytes = (int64_t)p->d * p->d * p->max_deg * 8 + idx * 4 + (int64_t)b * p->k * 4;
+            const int64_t gb = ceil_div(bytes, 8) * 8;
+            if (gb * (64 / g) > 64 * 1024) continue;
+            OwnArgs& A = D.own_args;
+            A.idx_ints = (int32_t)idx;
+            A.acc_doubles = p->d * p->d * p->max_deg;
+            A.group_bytes = (int32_t)gb;
+            const int rows = p->tune_owner_rows != 0 ? p->tune_owner_rows : (g == 64 && gb <= 3072 ? 2 : 1);
+            if (g == 64 && rows == 2 && jj <= 2 && gb * 2 + 8 * p->k * 4 <= 64 * 1024) {
+                D.path = jj == 1 ? kRows2J1 : kRows2J2;
+                lds = (size_t)gb * 2 + (size_t)8 * p->k * 4;
+                per = 2;
+            } else {
+                static const int32_t gpath[] = {kOwnG4, kOwnG8, kOwnG16, kOwnG32};
+                if (g < 64) {
+                    int gi = 0;
+                    while ((4 << gi) != g) ++gi;
+                    D.path = gpath[gi];
+                } else {
+                    D.path = jj == 1 ? kOwnG64J1 : jj == 2 ? kOwnG64J2 : jj == 4 ? kOwnG64J4
+                             : jj == 8 ? kOwnG64J8 : kOwnG64J16;
+                }
+                lds = (size_t)gb * (64 / g);
+                per = 64 / g;  // node rows per tile
+            }
+            return FEASM_OK;
+        }
+    }
+    // element paths: at most 64 lanes per element (one 64-lane block per tile)
+    const int64_t n2 = (int64_t)p->n * p->n;
+    int tpe = p->tune_atomic_tpe;
+    if (tpe == 0 || tpe > 64) tpe = n2 <= 16 ? 16 : n2 <= 64 ? 32 : 64;
+    if (tpe == 16 && n2 > 16) tpe = n2 <= 64 ? 32 : 64;
+    if (tpe == 32 && n2 > 64) tpe = 64;
+    const bool atomic = strategy == FEASM_SCATTER_ATOMIC || p->has_repeats;
+    D.path = atomic ? (tpe == 16 ? kElemA16 : tpe == 32 ? kElemA32 : kElemA64)
+                    : (tpe == 16 ? kElemP16 : tpe == 32 ? kElemP32 : kElemP64);
+    const int64_t lds_ints = 3 * (int64_t)p->k + 3 * (int64_t)p->n + (int64_t)p->k * p->k;
+    lds = (size_t)lds_ints * 4 * (64 / tpe);
+    if (lds > 64 * 1024) FEASM_FAIL(FEASM_ELIMIT, "assemble_batch: element too large for LDS");
+    D.asm_args.lds_ints = (int32_t)lds_ints;
+    per = 64 / tpe;  // elements per tile
+    return FEASM_OK;
+}
+
+int build_graph(feasm_batch* b) {
+    for (int i = 0; i < 3; ++i) {
+        FEASM_HIP(hipStreamCreateWithFlags(&b->streams[i], hipStreamNonBlocking));
+        FEASM_HIP(hipEventCreateWithFlags(&b->events[i], hipEventDisableTiming));
+    }
+    hipStream_t s0 = b->streams[0], s1 = b->streams[1], s2 = b->streams[2];
+    FEASM_HIP(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
+    const int32_t nl = (int32_t)b->launches.size();
+    k_batch_reset<<<1, 64, 0, s0>>>(b->d_counters, nl);
+    if (b->n_zero > 0 && !b->accumulate)
+        k_batch_zero<<<(unsigned)std::min<int64_t>(b->n_zero, 8192), 256, 0, s0>>>(b->d_zero, b->n_zero,
+                                                                                  b->d_values);
+    hipError_t err = hipEventRecord(b->events[0], s0);
+    // branch 1: phase 0, largest work first; branch 2: colour phases in order
+    bool used[3] = {true, false, false};
+    for (int br = 1; br <= 2 && err == hipSuccess; ++br) {
+        hipStream_t s = br == 1 ? s1 : s2;
+        bool any = false;
+        for (int32_t i = 0; i < nl; ++i) {
+            const Launch& L = b->launches[i];
+            if ((br == 1) != (L.phase == 0)) continue;
+            if (!any) {
+                err = hipStreamWaitEvent(s, b->events[0], 0);
+                any = true;
+            }
+            batch_kernel(b->fmt, L.path)<<<(unsigned)L.grid, 64, L.lds, s>>>(
+                b->d_meshes, b->d_ke, b->d_values, L.d_tiles, L.n_tiles, L.chunk,
+                b->d_counters + i);
+        }
+        if (any && err == hipSuccess) {
+            err = hipEventRecord(b->events[br], s);
+            if (err == hipSuccess) err = hipStreamWaitEvent(s0, b->events[br], 0);
+            used[br] = true;
+        }
+    }
+    (void)used;
+    const hipError_t le = hipGetLastError();
+    const hipError_t ce = hipStreamEndCapture(s0, &b->graph);
+    FEASM_HIP(err);
+    FEASM_HIP(le);
+    FEASM_HIP(ce);
+    FEASM_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    return FEASM_OK;
+}
+
+// Per-mesh-graph mode: the single-mesh numeric calls of every mesh, largest
+// first, dealt round-robin onto parallel graph branches.  The kernels take
+// the element-matrix and values pointers as arguments, so the graph is
+// recaptured whenever they change.
+int capture_per_mesh(feasm_batch* b, const double* const* ke, double* const* values) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    if (!b->streams[0]) {
+        FEASM_HIP(hipStreamCreateWithFlags(&b->streams[0], hipStreamNonBlocking));
+        FEASM_HIP(hipEventCreateWithFlags(&b->events[0], hipEventDisableTiming));
+        for (int i = 0; i < feasm_batch::kBranches; ++i) {
+            FEASM_HIP(hipStreamCreateWithFlags(&b->branch[i], hipStreamNonBlocking));
+            FEASM_HIP(hipEventCreateWithFlags(&b->branch_done[i], hipEventDisableTiming));
+        }
+    }
+    std::vector<int64_t> order(b->count);
+    for (int64_t m = 0; m < b->count; ++m) order[m] = m;
+    std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+        return b->patterns[x]->n_elem * b->patterns[x]->n * b->patterns[x]->n >
+               b->patterns[y]->n_elem * b->patterns[y]->n * b->patterns[y]->n;
+    });
+    hipStream_t s0 = b->streams[0];
+    FEASM_HIP(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
+    hipError_t err = hipEventRecord(b->events[0], s0);
+    for (int i = 0; i < feasm_batch::kBranches && err == hipSuccess; ++i)
+        err = hipStreamWaitEvent(b->branch[i], b->events[0], 0);
+    int rc = FEASM_OK;
+    const int scatter = FEASM_SCATTER_AUTO | (b->accumulate ? FEASM_ACCUMULATE : 0);
+    for (int64_t i = 0; i < b->count && err == hipSuccess && rc == FEASM_OK; ++i) {
+        const int64_t m = order[i];
+        rc = assemble_on_stream(b->patterns[m], b->fmt, ke[m], values[m], scatter,
+                                b->branch[i % feasm_batch::kBranches]);
+    }
+    for (int i = 0; i < feasm_batch::kBranches && err == hipSuccess; ++i) {
+        err = hipEventRecord(b->branch_done[i], b->branch[i]);
+        if (err == hipSuccess) err = hipStreamWaitEvent(s0, b->branch_done[i], 0);
+    }
+    const hipError_t ce = hipStreamEndCapture(s0, &b->graph);
+    if (rc != FEASM_OK) return rc;
+    FEASM_HIP(err);
+    FEASM_HIP(ce);
+    FEASM_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    return FEASM_OK;
+}
+
+void release_batch(feasm_batch* b) {
+    for (int i = 0; i < feasm_batch::kBranches; ++i) {
+        if (b->branch[i]) (void)hipStreamDestroy(b->branch[i]);
+        if (b->branch_done[i]) (void)hipEventDestroy(b->branch_done[i]);
+    }
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (int i = 0; i < 3; ++i) {
+        if (b->streams[i]) (void)hipStreamDestroy(b->streams[i]);
+        if (b->events[i]) (void)hipEventDestroy(b->events[i]);
+    }
+    void* arrs[] = {b->d_meshes, b->d_counters, b->d_zero, b->d_ke, b->d_values};
+    for (void* a : arrs)
+        if (a) (void)hipFree(a);
+    for (auto& L : b->launches)
+        if (L.d_tiles) (void)hipFree(L.d_tiles);
+    for (auto* c : b->d_colour_ptrs)
+        if (c) (void)hipFree(c);
+}
+
+int create(feasm_batch* b, const feasm_pattern* const* patterns, int64_t count, int fmt,
+           int accumulate) {
+    b->fmt = fmt;
+    b->count = count;
+    b->accumulate = accumulate;
+    (void)hipGetDevice(&b->device);
+    b->patterns.assign(patterns, patterns + count);
+    b->paths.assign(count, 0);
+    if (b->per_mesh_graph) {
+        for (int64_t m = 0; m < count; ++m) {
+            const feasm_pattern* p = patterns[m];
+            if (!p) FEASM_FAIL(FEASM_EINVAL, "batch_create: null handle at " + std::to_string(m));
+            if (!(p->flags & (fmt == FEASM_FMT_CSR ? FEASM_BUILD_CSR : FEASM_BUILD_CRAC)))
+                FEASM_FAIL(FEASM_EINVAL, "batch_create: mesh " + std::to_string(m) +
+                                             " lacks the requested format");
+        }
+        b->h_ke.assign(count, nullptr);
+        b->h_values.assign(count, nullptr);
+        return FEASM_OK;  // captured on the first assemble_batch
+    }
+    std::vector<MeshDesc> descs(count);
+    // (phase, path) -> tiles, work
+    std::vector<std::vector<std::vector<BatchTile>>> lists;  // [phase][path]
+    std::vector<std::vector<double>> work;
+    std::vector<std::vector<size_t>> ldsv;
+    auto ensure = [&](int32_t ph) {
+        while ((int32_t)lists.size() <= ph) {
+            lists.emplace_back(kNumPaths);
+            work.emplace_back(kNumPaths, 0.0);
+            ldsv.emplace_back(kNumPaths, (size_t)0);
+        }
+    };
+    ensure(0);
+    std::vector<ZeroChunk> zero;
+    b->d_colour_ptrs.assign(count, nullptr);
+    b->paths.assign(count, 0);
+    for (int64_t m = 0; m < count; ++m) {
+        const feasm_pattern* p = patterns[m];
+        if (!p) FEASM_FAIL(FEASM_EINVAL, "batch_create: null handle at " + std::to_string(m));
+        if (fmt == FEASM_FMT_CSR && !(p->flags & FEASM_BUILD_CSR))
+            FEASM_FAIL(FEASM_EINVAL, "batch_create: mesh " + std::to_string(m) + " has no CSR");
+        if (fmt == FEASM_FMT_CRAC && !(p->flags & FEASM_BUILD_CRAC))
+            FEASM_FAIL(FEASM_EINVAL, "batch_create: mesh " + std::to_string(m) + " has no CRAC");
+        int strategy = p->tune_strategy;
+        if (strategy == FEASM_SCATTER_AUTO) strategy = FEASM_SCATTER_OWNER;
+        if (strategy == FEASM_SCATTER_COLOURED && !(p->flags & FEASM_BUILD_COLOUR))
+            FEASM_FAIL(FEASM_EINVAL, "batch_create: coloured strategy needs a coloured handle");
+        MeshDesc& D = descs[m];
+        std::memset(&D, 0, sizeof(D));
+        size_t lds = 0;
+        int64_t per = 1;
+        int rc = mesh_path(p, fmt, strategy, D, lds, per);
+        if (rc != FEASM_OK && strategy == FEASM_SCATTER_OWNER) {
+            strategy = FEASM_SCATTER_ATOMIC;  // rows too long for LDS: fall back
+            rc = mesh_path(p, fmt, strategy, D, lds, per);
+        }
+        if (rc != FEASM_OK) return rc;
+        b->paths[m] = D.path;
+        AsmArgs& A = D.asm_args;
+        A.conn = p->conn;
+        A.k = p->k;
+        A.d = p->d;
+        A.n = p->n;
+        A.row_ptr = p->row_ptr;
+        A.col_idx = p->col_idx;
+        A.crac_row_ptr = p->crac_row_ptr;
+        A.ca = p->ca;
+        A.count = p->n_elem;
+        A.elem_list = nullptr;
+        OwnArgs& O = D.own_args;
+        O.conn = p->conn;
+        O.k = p->k;
+        O.d = p->d;
+        O.n = p->n;
+        O.inc_ptr = p->inc_ptr;
+        O.inc_q = p->inc_q;
+        O.inc_elem = p->inc_elem;
+        O.inc_local = p->inc_local;
+        O.row_ptr = p->row_ptr;
+        O.col_idx = p->col_idx;
+        O.crac_row_ptr = p->crac_row_ptr;
+        O.ca = p->ca;
+        O.n_nodes = p->n_nodes;
+        O.accumulate = accumulate;
+        O.persistent = 0;
+        const double elem_cost = (double)p->n * p->n;
+        if (D.path >= kElemA16 && !accumulate)
+            for (int64_t f = 0; f < p->nnz; f += kZeroChunk)
+                zero.push_back({(int32_t)m, 0, f, std::min<int64_t>(kZeroChunk, p->nnz - f)});
+        if (strategy == FEASM_SCATTER_COLOURED) {
+            A.elem_list = p->colour_elems;
+            const int32_t nc = p->n_colours;
+            FEASM_HIP(hipMalloc((void**)&b->d_colour_ptrs[m], sizeof(int64_t) * (nc + 1)));
+            FEASM_HIP(hipMemcpy(b->d_colour_ptrs[m], p->colour_ptr.data(),
+                                sizeof(int64_t) * (nc + 1), hipMemcpyHostToDevice));
+            D.colour_ptr = b->d_colour_ptrs[m];
+            ensure(nc);
+            for (int32_t c = 0; c < nc; ++c) {
+                const int64_t sz = p->colour_ptr[c + 1] - p->colour_ptr[c];
+                for (int64_t i = 0; i < ceil_div(sz, per); ++i)
+                    lists[c + 1][D.path].push_back({(int32_t)m, c, i});
+                work[c + 1][D.path] += elem_cost * sz;
+                ldsv[c + 1][D.path] = std::max(ldsv[c + 1][D.path], lds);
+            }
+        } else {
+            const int64_t units = D.path >= kElemA16 ? p->n_elem : p->n_nodes;
+            for (int64_t i = 0; i < ceil_div(units, per); ++i)
+                lists[0][D.path].push_back({(int32_t)m, -1, i});
+            work[0][D.path] += elem_cost * p->n_elem;
+            ldsv[0][D.path] = std::max(ldsv[0][D.path], lds);
+        }
+    }
+    FEASM_HIP(hipMalloc((void**)&b->d_meshes, sizeof(MeshDesc) * count));
+    FEASM_HIP(hipMemcpy(b->d_meshes, descs.data(), sizeof(MeshDesc) * count, hipMemcpyHostToDevice));
+    int cus = 0;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
+    cus = std::max(cus, 1);
+    b->n_phases = (int32_t)lists.size();
+    for (int32_t ph = 0; ph < (int32_t)lists.size(); ++ph) {
+        std::vector<Launch> here;
+        for (int32_t path = 0; path < kNumPaths; ++path) {
+            auto& tl = lists[ph][path];
+            if (tl.empty()) continue;
+            Launch L;
+            L.phase = ph;
+            L.path = path;
+            L.n_tiles = (int64_t)tl.size();
+            L.lds = ldsv[ph][path];
+            L.work = work[ph][path];
+            if (L.lds > 64 * 1024) FEASM_FAIL(FEASM_ELIMIT, "batch_create: LDS per block exceeds 64 KiB");
+            int per_cu = 0;
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel(fmt, path), 64,
+                                                               L.lds);
+            const int64_t cap = (int64_t)cus * std::max(per_cu, 1);
+            L.chunk = std::max<int64_t>(1, std::min<int64_t>(32, L.n_tiles / (cap * 8)));
+            L.grid = std::max<int64_t>(1, std::min<int64_t>(cap, ceil_div(L.n_tiles, L.chunk)));
+            FEASM_HIP(hipMalloc((void**)&L.d_tiles, sizeof(BatchTile) * tl.size()));
+            FEASM_HIP(hipMemcpy(L.d_tiles, tl.data(), sizeof(BatchTile) * tl.size(),
+                                hipMemcpyHostToDevice));
+            here.push_back(L);
+        }
+        std::stable_sort(here.begin(), here.end(),
+                         [](const Launch& x, const Launch& y) { return x.work > y.work; });
+        b->launches.insert(b->launches.end(), here.begin(), here.end());
+    }
+    FEASM_HIP(hipMalloc((void**)&b->d_counters,
+                        sizeof(unsigned long long) * std::max<size_t>(b->launches.size(), 1)));
+    if ((int64_t)b->launches.size() > 64)
+        FEASM_FAIL(FEASM_ELIMIT, "batch_create: more than 64 (phase, path) launches");
+    b->n_zero = (int64_t)zero.size();
+    if (!zero.empty()) {
+        FEASM_HIP(hipMalloc((void**)&b->d_zero, sizeof(ZeroChunk) * zero.size()));
+        FEASM_HIP(hipMemcpy(b->d_zero, zero.data(), sizeof(ZeroChunk) * zero.size(),
+                            hipMemcpyHostToDevice));
+    }
+    FEASM_HIP(hipMalloc((void**)&b->d_ke, sizeof(double*) * count));
+    FEASM_HIP(hipMalloc((void**)&b->d_values, sizeof(double*) * count));
+    FEASM_HIP(hipMemset(b->d_ke, 0, sizeof(double*) * count));
+    FEASM_HIP(hipMemset(b->d_values, 0, sizeof(double*) * count));
+    b->h_ke.assign(count, nullptr);
+    b->h_values.assign(count, nullptr);
+    return build_graph(b);
+}
+
+}  // namespace
+}  // namespace feasm
+
+extern "C" int batch_create(const feasm_pattern* const* patterns, int64_t count, int fmt,
+                            uint32_t flags, feasm_batch** out) {
+    using namespace feasm;
+    if (!out) FEASM_FAIL(FEASM_EINVAL, "batch_create: out is NULL");
+    *out = nullptr;
+    if (!patterns || count <= 0) FEASM_FAIL(FEASM_EINVAL, "batch_create: no meshes");
+    if (count > INT32_MAX) FEASM_FAIL(FEASM_EOVERFLOW, "batch_create: too many meshes");
+    if (fmt != FEASM_FMT_CSR && fmt != FEASM_FMT_CRAC)
+        FEASM_FAIL(FEASM_EINVAL, "batch_create: fmt must be FEASM_FMT_CSR or FEASM_FMT_CRAC");
+    if (flags & ~(uint32_t)(FEASM_ACCUMULATE | FEASM_BATCH_PER_MESH_GRAPH))
+        FEASM_FAIL(FEASM_EINVAL, "batch_create: unknown flag");
+    feasm_batch* b = new (std::nothrow) feasm_batch();
+    if (!b) FEASM_FAIL(FEASM_ENOMEM, "batch_create: out of host memory");
+    b->per_mesh_graph = (flags & FEASM_BATCH_PER_MESH_GRAPH) ? 1 : 0;
+    const int rc = create(b, patterns, count, fmt, (flags & FEASM_ACCUMULATE) ? 1 : 0);
+    if (rc != FEASM_OK) {
+        (void)hipDeviceSynchronize();
+        release_batch(b);
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return FEASM_OK;
+}
+
+extern "C" int assemble_batch(feasm_batch* b, const double* const* ke, double* const* values,
+                              hipStream_t stream) {
+    using namespace feasm;
+    if (!b) FEASM_FAIL(FEASM_EINVAL, "assemble_batch: null batch");
+    if (!ke || !values) FEASM_FAIL(FEASM_EINVAL, "assemble_batch: ke or values table is NULL");
+    bool changed = false;
+    for (int64_t m = 0; m < b->count; ++m) {
+        if (!ke[m] || !values[m])
+            FEASM_FAIL(FEASM_EINVAL, "assemble_batch: null pointer for mesh " + std::to_string(m));
+        changed |= ke[m] != b->h_ke[m] || values[m] != b->h_values[m];
+    }
+    if (b->per_mesh_graph) {
+        if (changed || !b->exec) {
+            b->h_ke.assign(ke, ke + b->count);
+            b->h_values.assign(values, values + b->count);
+            const int rc = capture_per_mesh(b, ke, values);
+            if (rc != FEASM_OK) return rc;
+        }
+        FEASM_HIP(hipGraphLaunch(b->exec, stream));
+        return FEASM_OK;
+    }
+    if (changed) {
+        // the tables are read by the graph's kernels: update them in stream order
+        b->h_ke.assign(ke, ke + b->count);
+        b->h_values.assign(values, values + b->count);
+        FEASM_HIP(hipMemcpyAsync(b->d_ke, b->h_ke.data(), sizeof(double*) * b->count,
+                                 hipMemcpyHostToDevice, stream));
+        FEASM_HIP(hipMemcpyAsync(b->d_values, b->h_values.data(), sizeof(double*) * b->count,
+                                 hipMemcpyHostToDevice, stream));
+        FEASM_HIP(hipStreamSynchronize(stream));  // host tables may change before the copy runs
+    }
+    FEASM_HIP(hipGraphLaunch(b->exec, stream));
+    return FEASM_OK;
+}
+
+extern "C" int batch_info(const feasm_batch* b, int32_t* n_phases, int64_t* n_tiles,
+                          int64_t* grid, int32_t* paths) {
+    if (!b) FEASM_FAIL(FEASM_EINVAL, "batch_info: null batch");
+    if (n_phases) *n_phases = b->n_phases;
+    int64_t t = 0, g = 0;
+    for (const auto& L : b->launches) {
+        t += L.n_tiles;
+        g = std::max(g, L.grid);
+    }
+    if (n_tiles) *n_tiles = t;
+    if (grid) *grid = g;
+    if (paths)
+        for (int64_t m = 0; m < b->count; ++m) paths[m] = b->paths[m];
+    return FEASM_OK;
+}
+
+extern "C" void batch_free(feasm_batch* b) {
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    feasm::release_batch(b);
+    delete b;
+}

@@ -87,6 +87,7 @@ struct feasm_pattern {
     int32_t tune_atomic_tpe = 0;           // threads per element of the atomic/coloured scatter
     int32_t tune_owner_rows = 0;           // >1: node rows per wavefront (row-owned, large elements)
     int32_t tune_owner_batch = 0;          // incidence entries loaded per batch (8 or 16)
+    int32_t tune_strategy = 0;             // what FEASM_SCATTER_AUTO resolves to (0: row-owned)
 };
 
 namespace feasm {
@@ -102,6 +103,10 @@ int exclusive_scan(const T* in, int64_t n, int64_t* out, int64_t* scratch, hipSt
 
 // Colouring (colour.hip): fills p->elem_colour, colour_elems, colour_ptr, n_colours.
 int build_colouring(feasm_pattern* p, hipStream_t s);
+
+// The numeric phase of one mesh on a stream (asynchronous; used by batches).
+int assemble_on_stream(const feasm_pattern* p, int fmt, const double* ke, double* values,
+                       int scatter, hipStream_t s);
 
 // Free every device array of the handle.
 void release_pattern(feasm_pattern* p);

@@ -1,0 +1,176 @@
+"""Batched persistent assembly, the autotuner and the device generator (GPU)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from fe_inputs import matrices, meshes, philox
+from tests._checks import assert_values_close
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def feasm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2012_00585_amd as f
+
+    f.load()
+    return f
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("recipe,n", [(0, 4), (0, 9), (1, 24), (1, 30), (1, 3)])
+def test_device_generator_matches_host_twin(feasm, recipe, n):
+    seed, e0, E = 2 ** 33 + 17, 1000, 77
+    say(f"[gen] recipe={recipe} n={n}")
+    dev = feasm.generate_ke(recipe, E, n, seed, e0)
+    host = (philox.ke_laplacian if recipe == 0 else philox.ke_spd)(E, n, seed, e0)
+    assert (_np(dev) == host).all()
+
+
+def _mix():
+    """A small batch of uneven meshes of several element types."""
+    rep_conn, rep_nn = meshes.quad_mesh(5)
+    rep_conn = rep_conn.copy()
+    rep_conn[7, 3] = rep_conn[7, 1]
+    return [
+        ("quad7", *meshes.quad_mesh(7), 1),
+        ("quad20", *meshes.quad_mesh(20), 1),
+        ("hex3", *meshes.hex_mesh(3), 3),
+        ("hex6", *meshes.hex_mesh(6), 3),
+        ("tet2", *meshes.tet10_mesh(2, perm_seed=4), 3),
+        ("q3quad3_d2", *meshes.qp_quad_mesh(3, 3), 2),
+        ("repeated", rep_conn, rep_nn, 2),
+        ("hex5_d1", *meshes.hex_mesh(5), 1),
+    ]
+
+
+STRATS = {
+    "owner": (3, 0),
+    "atomic16": (1, 16),
+    "atomic64": (1, 64),
+    "coloured32": (2, 32),
+    "coloured64": (2, 64),
+}
+
+
+@pytest.mark.parametrize("fmt", [0, 1])
+@pytest.mark.parametrize("assign", ["owner", "mixed"])
+@pytest.mark.parametrize("per_mesh_graph", [False, True])
+def test_batch_matches_oracle(feasm, orc, fmt, assign, per_mesh_graph):
+    from paper_2012_00585_amd.batch import Batch
+
+    dev = torch.device("cuda:0")
+    mix = _mix()
+    pats, kes, vals, refs = [], [], [], []
+    for i, (name, conn, nn, d) in enumerate(mix):
+        E, k = conn.shape
+        p = feasm.pattern_build(torch.from_numpy(conn).to(dev), d, nn,
+                                feasm.BUILD_CSR | feasm.BUILD_CRAC | feasm.BUILD_COLOUR)
+        strat = "owner" if assign == "owner" else list(STRATS)[i % len(STRATS)]
+        sc, tpe = STRATS[strat]
+        if tpe and k * d * k * d > 16 * tpe:
+            tpe = 64
+        p.tune(feasm.TUNE_STRATEGY, sc)
+        p.tune(feasm.TUNE_THREADS_PER_ELEM, tpe)
+        ke = matrices.ke_spd(E, k * d, seed=i)
+        rp, ci = orc.pattern(conn, d, nn)
+        ov, oa = orc.assemble(conn, d, ke, rp, ci)
+        pats.append(p)
+        kes.append(torch.from_numpy(ke).to(dev))
+        vals.append(torch.full((p.nnz,), np.nan, dtype=torch.float64, device=dev))
+        refs.append((name, strat, ov, oa))
+    b = Batch(pats, fmt=fmt, per_mesh_graph=per_mesh_graph)
+    info = b.info()
+    say(f"[batch] fmt={fmt} assign={assign} per_mesh_graph={per_mesh_graph} {info}")
+    for rep in range(3):
+        if rep == 2:  # new buffers: the pointer table is refreshed
+            kes = [k.clone() for k in kes]
+            vals = [torch.full_like(v, np.nan) for v in vals]
+        b.assemble(kes, vals)
+        torch.cuda.synchronize()
+        for (name, strat, ov, oa), v in zip(refs, vals):
+            got = _np(v)
+            if strat == "owner" and name != "repeated":
+                assert (got == ov).all(), (name, rep)
+            else:
+                assert_values_close(got, ov, oa, what=f"{name} {strat} rep{rep}")
+    # same values as the single-mesh calls
+    fn = feasm.assemble_csr if fmt == 0 else feasm.assemble_crac
+    for p, k, v, (name, strat, ov, oa) in zip(pats, kes, vals, refs):
+        single = _np(fn(p, k))
+        if strat == "owner" and name != "repeated":
+            assert (single == _np(v)).all(), name
+    b.free()
+    for p in pats:
+        p.free()
+
+
+def test_batch_accumulate_and_integer_exact(feasm, orc):
+    from paper_2012_00585_amd.batch import Batch
+
+    dev = torch.device("cuda:0")
+    mix = _mix()[:5]
+    pats, kes, vals, refs = [], [], [], []
+    for i, (name, conn, nn, d) in enumerate(mix):
+        E, k = conn.shape
+        p = feasm.pattern_build(torch.from_numpy(conn).to(dev), d, nn,
+                                feasm.BUILD_CSR | feasm.BUILD_CRAC | feasm.BUILD_COLOUR)
+        p.tune(feasm.TUNE_STRATEGY, [3, 1, 2, 3, 1][i])
+        ke = matrices.ke_small_int(E, k * d, seed=i)
+        rp, ci = orc.pattern(conn, d, nn)
+        ov, _ = orc.assemble(conn, d, ke, rp, ci)
+        pats.append(p)
+        kes.append(torch.from_numpy(ke).to(dev))
+        vals.append(torch.full((p.nnz,), 5.0, dtype=torch.float64, device=dev))
+        refs.append(ov)
+    for per_mesh_graph in (False, True):
+        for v in vals:
+            v.fill_(5.0)
+        b = Batch(pats, fmt=1, accumulate=True, per_mesh_graph=per_mesh_graph)
+        b.assemble(kes, vals)
+        for v, ov in zip(vals, refs):
+            assert (_np(v) == ov + 5.0).all()
+        b.free()
+    for p in pats:
+        p.free()
+
+
+def test_autotune_keeps_results(feasm, orc):
+    from paper_2012_00585_amd import autotune
+    from paper_2012_00585_amd.batch import Batch
+
+    dev = torch.device("cuda:0")
+    mix = [("quad30", *meshes.quad_mesh(30), 1), ("quad40", *meshes.quad_mesh(40), 1),
+           ("hex8", *meshes.hex_mesh(8), 3), ("hex10", *meshes.hex_mesh(10), 3)]
+    pats, kes, vals, refs = [], [], [], []
+    for i, (name, conn, nn, d) in enumerate(mix):
+        E, k = conn.shape
+        p = feasm.pattern_build(torch.from_numpy(conn).to(dev), d, nn,
+                                feasm.BUILD_CSR | feasm.BUILD_CRAC | feasm.BUILD_COLOUR)
+        ke = matrices.ke_small_int(E, k * d, seed=i)
+        rp, ci = orc.pattern(conn, d, nn)
+        refs.append(orc.assemble(conn, d, ke, rp, ci)[0])
+        pats.append(p)
+        kes.append(torch.from_numpy(ke).to(dev))
+        vals.append(torch.zeros(p.nnz, dtype=torch.float64, device=dev))
+    choices = autotune.autotune(pats, kes, vals, fmt=1, reps=2, warmup=1, log=say)
+    assert len(choices) >= 2 and all(len(v) >= 3 for v in choices.values())
+    b = Batch(pats, fmt=1)
+    b.assemble(kes, vals)
+    for v, ov in zip(vals, refs):
+        assert (_np(v) == ov).all()
+    b.free()
+    for p in pats:
+        p.free()
