@@ -142,9 +142,12 @@ int assemble_crac(const feasm_pattern* p, const double* ke, double* values, int 
  * (Section 3 intro: between assemblies the values are reset to zero and the
  * pattern is kept).  `fmt` is FEASM_FMT_CSR or FEASM_FMT_CRAC.  Returns the
  * same values as assemble_<fmt> with the same arguments (bitwise for the
- * coloured strategy; within FP64 reordering for the atomic one).  The first
- * call may build a per-handle lookup cache on the device (hence the
- * non-const handle); calls on one handle must not overlap.  Asynchronous.
+ * row-owned and coloured strategies; within FP64 reordering for the atomic
+ * one).  With the atomic or coloured strategy the first call on a handle
+ * records each element's lookup results on the device and synchronises
+ * `stream` (hence the non-const handle); later calls, on any stream and
+ * concurrently, read the record instead of searching.  The first call must
+ * not race another call on the same handle.  Otherwise asynchronous.
  */
 int reassemble_values(feasm_pattern* p, int fmt, const double* ke, double* values, int scatter,
                       hipStream_t stream);

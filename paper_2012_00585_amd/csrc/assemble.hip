@@ -26,6 +26,7 @@ namespace feasm {
 
 struct OffsetCache {
     int fmt = -1;
+    bool valid = false;       // filled completely by an element-path assembly
     int32_t* base = nullptr;  // dev [n_elem][k][k]: run offsets inside each row node's row
 };
 
@@ -334,24 +335,46 @@ extern "C" int reassemble_values(feasm_pattern* p, int fmt, const double* ke, do
     if (!p) FEASM_FAIL(FEASM_EINVAL, "reassemble_values: null handle");
     if (fmt != FEASM_FMT_CSR && fmt != FEASM_FMT_CRAC)
         FEASM_FAIL(FEASM_EINVAL, "reassemble_values: fmt must be FEASM_FMT_CSR or FEASM_FMT_CRAC");
-    // The first call on a format performs the lookups and records them; later
-    // calls read the recorded offsets instead of searching.
-    if (!p->cache || p->cache->fmt != fmt) {
-        release_cache(p);
-        p->cache = new (std::nothrow) OffsetCache();
-        if (!p->cache) FEASM_FAIL(FEASM_ENOMEM, "reassemble_values: out of host memory");
-        const size_t bytes = sizeof(int32_t) * (size_t)p->n_elem * p->k * p->k;
-        hipError_t e = hipMalloc((void**)&p->cache->base, bytes);
-        if (e != hipSuccess) {
-            release_cache(p);
-            FEASM_FAIL(FEASM_ENOMEM, "reassemble_values: cannot allocate lookup cache");
-        }
-        p->cache->fmt = fmt;
-        return assemble_impl(p, fmt, ke, values, scatter, nullptr, p->cache->base, stream,
-                             "reassemble_values");
+    if (fmt == FEASM_FMT_CSR && !(p->flags & FEASM_BUILD_CSR))
+        FEASM_FAIL(FEASM_EINVAL, "reassemble_values: handle was built without CSR");
+    if (fmt == FEASM_FMT_CRAC && !(p->flags & FEASM_BUILD_CRAC))
+        FEASM_FAIL(FEASM_EINVAL, "reassemble_values: handle was built without CRAC");
+    // The element-centric strategies record their (row node, run) offsets on
+    // the first call and read them afterwards instead of searching; the
+    // row-owned strategy searches rows staged in LDS and needs no record.
+    int strategy = scatter & ~FEASM_ACCUMULATE;
+    if (strategy == FEASM_SCATTER_AUTO) {
+        strategy = p->tune_strategy;
+        if (strategy == FEASM_SCATTER_AUTO ||
+            (strategy == FEASM_SCATTER_OWNER && !owner_fits(p, fmt)))
+            strategy = owner_fits(p, fmt) ? FEASM_SCATTER_OWNER : FEASM_SCATTER_ATOMIC;
+        scatter = strategy | (scatter & FEASM_ACCUMULATE);
     }
-    return assemble_impl(p, fmt, ke, values, scatter, p->cache->base, nullptr, stream,
-                         "reassemble_values");
+    if (strategy == FEASM_SCATTER_OWNER || strategy == FEASM_SCATTER_AUTO)
+        return assemble_impl(p, fmt, ke, values, scatter, nullptr, nullptr, stream,
+                             "reassemble_values");
+    if (p->cache && p->cache->valid && p->cache->fmt == fmt)
+        return assemble_impl(p, fmt, ke, values, scatter, p->cache->base, nullptr, stream,
+                             "reassemble_values");
+    release_cache(p);
+    p->cache = new (std::nothrow) OffsetCache();
+    if (!p->cache) FEASM_FAIL(FEASM_ENOMEM, "reassemble_values: out of host memory");
+    const size_t bytes = sizeof(int32_t) * (size_t)p->n_elem * p->k * p->k;
+    if (hipMalloc((void**)&p->cache->base, bytes) != hipSuccess) {
+        release_cache(p);
+        FEASM_FAIL(FEASM_ENOMEM, "reassemble_values: cannot allocate lookup cache");
+    }
+    p->cache->fmt = fmt;
+    const int rc = assemble_impl(p, fmt, ke, values, scatter, nullptr, p->cache->base, stream,
+                                 "reassemble_values");
+    if (rc != FEASM_OK) {
+        release_cache(p);
+        return rc;
+    }
+    // the record is complete before any call, on any stream, may read it
+    FEASM_HIP(hipStreamSynchronize(stream));
+    p->cache->valid = true;
+    return FEASM_OK;
 }
 
 extern "C" int pattern_tune(feasm_pattern* p, int key, int64_t value) {

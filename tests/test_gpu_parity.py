@@ -343,3 +343,24 @@ def test_atomic_threads_per_element_tuning(feasm, orc):
     with pytest.raises(feasm.FeasmError):
         p.tune(99, 1)
     p.free()
+
+
+def test_reassembly_record_after_row_owned_calls(feasm, orc):
+    # the row-owned strategy records no lookups; a later atomic or coloured
+    # re-assembly on the same handle must record its own before reading them
+    conn, nn = meshes.tet10_mesh(3, perm_seed=8)
+    d = 3
+    E, k = conn.shape
+    ke = matrices.ke_small_int(E, k * d, seed=4)
+    dev = torch.device("cuda:0")
+    p = feasm.pattern_build(torch.from_numpy(conn).to(dev), d, nn,
+                            feasm.BUILD_CSR | feasm.BUILD_CRAC | feasm.BUILD_COLOUR)
+    rp, ci = orc.pattern(conn, d, nn)
+    ov, _ = orc.assemble(conn, d, ke, rp, ci)
+    ke_d = torch.from_numpy(ke).to(dev)
+    for fmt in (feasm.FMT_CRAC, feasm.FMT_CSR):
+        for sc in (feasm.SCATTER_OWNER, feasm.SCATTER_OWNER, feasm.SCATTER_ATOMIC,
+                   feasm.SCATTER_ATOMIC, feasm.SCATTER_COLOURED, feasm.SCATTER_OWNER):
+            v = _np(feasm.reassemble_values(p, fmt, ke_d, scatter=sc))
+            assert (v == ov).all(), (fmt, sc)
+    p.free()
