@@ -127,7 +127,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="hex64",
-                    choices=["hex64", "quad64", "tet40", "batch512"])
+                    choices=["hex64", "quad64", "tet40", "batch512", "serve"])
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-rate", type=float, default=2000.0, help="mean arrivals per second")
+    ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--batch-count", type=int, default=512,
                     help="batch512: number of meshes (the mix is the first N of the 512)")
     ap.add_argument("--cpu-reps", type=int, default=3, help="0 skips the oracle baseline")
@@ -159,6 +162,8 @@ def main():
         del src, dst
     if args.workload == "batch512":
         return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
     w, wdesc = workload(args.workload)
     log(f"[bench] {wdesc}: generating element matrices")
     ke = w.ke()
@@ -375,6 +380,79 @@ def bench_batch(args):
         "build_s": build_s,
     }
     b.free()
+    for p in pats:
+        p.free()
+    print(json.dumps(line), flush=True)
+
+
+def bench_serve(args):
+    """Poisson request stream over the batch mix: assembly + 10 re-assemblies each."""
+    import torch
+
+    import paper_2012_00585_amd as feasm
+    from fe_inputs import configs, meshes
+    from paper_2012_00585_amd import autotune
+    from paper_2012_00585_amd.serve import Request, Server
+
+    dev = torch.device("cuda:0")
+    specs = configs.batch_mix()[: args.batch_count]
+    log(f"[bench] serve: building {len(specs)} resident patterns")
+    pats, recipes = [], []
+    for sp in specs:
+        conn, nn = meshes.quad_mesh(sp.size) if sp.kind == "quad" else meshes.hex_mesh(sp.size)
+        pats.append(feasm.pattern_build(torch.from_numpy(conn).to(dev), sp.dofs_per_node, nn,
+                                        feasm.BUILD_CSR | feasm.BUILD_CRAC))
+        recipes.append(feasm.RECIPE_LAPLACIAN if sp.kind == "quad" else feasm.RECIPE_SPD)
+    # one tuning pass per size class on generated matrices
+    classes = {}
+    for i, p in enumerate(pats):
+        classes.setdefault(autotune.size_class(p), []).append(i)
+    for cls, members in classes.items():
+        rep = max(members, key=lambda i: pats[i].n_elem)
+        ke = feasm.generate_ke(recipes[rep], pats[rep].n_elem, pats[rep].n, 1)
+        vals = torch.empty(pats[rep].nnz, dtype=torch.float64, device=dev)
+        ranked = autotune.tune_one(pats[rep], ke, vals, feasm.FMT_CRAC, reps=3, warmup=1)
+        for i in members:
+            autotune.apply(pats[i], ranked[0])
+        del ke, vals
+
+    def stream(rate, seconds, seed):
+        n = int(rate * seconds)
+        t = configs.arrival_times(n, 1.0 / rate, seed=seed)
+        rng = np.random.default_rng(seed + 1)
+        mesh = rng.integers(len(specs), size=n)
+        rs = rng.integers(1 << 40, size=n)
+        return [Request(i, float(t[i]), int(mesh[i]), int(rs[i]), 10) for i in range(n)]
+
+    def server(slots):
+        srv = Server(fmt=feasm.FMT_CRAC, slots=slots, hbm_budget=96 << 30)
+        for i, p in enumerate(pats):
+            srv.register(i, p, recipes[i])
+        return srv
+
+    out = {}
+    for name, rate, seconds, slots in (
+            ("continuous", args.serve_rate, args.serve_seconds, args.serve_slots),
+            ("continuous_500", 500.0, args.serve_seconds / 2, args.serve_slots),
+            ("fifo_one_per_launch", args.serve_rate, args.serve_seconds / 5, 1)):
+        log(f"[bench] serve {name}: {rate:.0f} req/s for {seconds:.1f} s, {slots} slot(s); warm-up")
+        server(slots).run(stream(rate, 1.0, seed=99))
+        res = server(slots).run(stream(rate, seconds, seed=0))
+        log(f"[bench]   {res}")
+        out[name] = res
+    c = out["continuous"]
+    line = {
+        "metric": "served element matrices/s; p50/p99 re-assembly latency",
+        "value": c["element_matrices_per_s"], "unit": "element matrices/s", "n_gpus": 1,
+        "steps": c["requests"], "warmup": 1, "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"serving: Poisson arrivals at {args.serve_rate:.0f} req/s over "
+                               f"the {len(specs)}-mesh batch mix, assembly + 10 re-assemblies "
+                               f"with device-generated Ke, resident CRAC patterns",
+                   "slots": args.serve_slots, "seconds": args.serve_seconds},
+        "scenarios": out,
+    }
     for p in pats:
         p.free()
     print(json.dumps(line), flush=True)

@@ -8,15 +8,15 @@ written from that definition; the device library has its own.  Both feed the
 same recipes, whose arithmetic is exact or a fixed sequence of correctly
 rounded IEEE operations, so both produce the same bits.
 
-Recipes, for element e of a generation call with element offset e0, seed s
-(key = (s mod 2^32, s div 2^32)), counter (i, (e+e0) mod 2^32, (e+e0) div 2^32, stream):
+Entry i = r*n + s of element e takes 32-bit word i mod 4 of Philox(counter
+(i div 4, (e+e0) mod 2^32, (e+e0) div 2^32, recipe), key (seed mod 2^32,
+seed div 2^32)); u = word * 2^-32.
 
-* laplacian: for r < s, K_rs = 2 u - 1 with u = x0 * 2^-32 from counter
-  (r*n + s, ., ., 0); mirrored; K_rr = -sum_{s != r} K_rs in increasing s.
-* spd: B_ij = (((u0 + u1) + u2) + u3 - 2) * sqrt(3) (a unit-variance
-  Irwin-Hall variate) from counter (i*n + j, ., ., 1); K_rs =
-  (sum_t B_rt B_st, t increasing, products then sums, no fused multiply-add)
-  / n, plus 1 on the diagonal.
+* laplacian (recipe 0): K_rs = 2u - 1 for r < s, mirrored;
+  K_rr = -sum_{s != r} K_rs in increasing s.
+* spd (recipe 1): B_rs = (u - 1/2) * sqrt(12) (unit variance);
+  K_rs = (sum_t B_rt B_st, t increasing, products then sums, no fused
+  multiply-add) / n, plus 1 on the diagonal.
 """
 from __future__ import annotations
 
@@ -50,20 +50,24 @@ def philox4x32_10(c0, c1, c2, c3, k0, k1):
     return c0, c1, c2, c3
 
 
-def _counters(E, n, e0, stream):
+SQRT12 = 3.4641016151377544
+
+
+def _uniforms(E, n, e0, recipe, seed):
+    """[E, n*n] uniforms u in [0, 1): word i mod 4 of the call for i div 4."""
+    k0, k1 = seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF
+    calls = (n * n + 3) // 4
     e = np.arange(E, dtype=np.uint64) + np.uint64(e0)
-    i = np.arange(n * n, dtype=np.uint64)
-    c0 = np.broadcast_to(i[None, :], (E, n * n)).astype(np.uint32)
-    c1 = np.broadcast_to((e & MASK)[:, None], (E, n * n)).astype(np.uint32)
-    c2 = np.broadcast_to((e >> np.uint64(32))[:, None], (E, n * n)).astype(np.uint32)
-    c3 = np.full((E, n * n), stream, dtype=np.uint32)
-    return c0, c1, c2, c3
+    c0 = np.broadcast_to(np.arange(calls, dtype=np.uint32)[None, :], (E, calls))
+    c1 = np.broadcast_to((e & MASK).astype(np.uint32)[:, None], (E, calls))
+    c2 = np.broadcast_to((e >> np.uint64(32)).astype(np.uint32)[:, None], (E, calls))
+    c3 = np.full((E, calls), recipe, dtype=np.uint32)
+    w = np.stack(philox4x32_10(c0, c1, c2, c3, k0, k1), axis=-1).reshape(E, 4 * calls)
+    return w[:, : n * n].astype(np.float64) * 2.0 ** -32
 
 
 def ke_laplacian(E, n, seed, e0=0):
-    k0, k1 = seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF
-    x0, _, _, _ = philox4x32_10(*_counters(E, n, e0, 0), k0, k1)
-    u = x0.astype(np.float64) * 2.0 ** -32
+    u = _uniforms(E, n, e0, 0, seed)
     V = (2.0 * u - 1.0).reshape(E, n, n)
     K = np.zeros((E, n, n))
     iu = np.triu_indices(n, 1)
@@ -79,10 +83,8 @@ def ke_laplacian(E, n, seed, e0=0):
 
 
 def ke_spd(E, n, seed, e0=0):
-    k0, k1 = seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF
-    x = philox4x32_10(*_counters(E, n, e0, 1), k0, k1)
-    u = [xi.astype(np.float64) * 2.0 ** -32 for xi in x]
-    B = ((((u[0] + u[1]) + u[2]) + u[3] - 2.0) * SQRT3).reshape(E, n, n)
+    u = _uniforms(E, n, e0, 1, seed)
+    B = ((u - 0.5) * SQRT12).reshape(E, n, n)
     acc = np.zeros((E, n, n))
     for t in range(n):
         acc = acc + B[:, :, None, t] * B[:, None, :, t]

@@ -258,6 +258,41 @@ void batch_free(feasm_batch* b);
 /* Thread-local message describing the latest failed call on this thread. */
 const char* last_error(void);
 
+/*
+ * Serving engine: requests for one assembly followed by n_reassembly
+ * value-only re-assemblies of a registered mesh (whose pattern stays
+ * resident), each iteration with fresh element matrices from generate_ke
+ * (recipe of the mesh, key seed*1000003 + iteration*7919 + 1 mod 2^64).
+ * Continuous batching: arriving requests are admitted FIFO into free slots
+ * (each with its own streams and buffers) whenever the sum of admitted
+ * footprints (2 element-matrix buffers + values) stays within hbm_budget
+ * (<= 0: no limit; a request is always admitted when nothing else runs);
+ * every slot issues its next iteration as soon as the previous completes,
+ * so admitted requests overlap on the device.  Runs until every request is
+ * done; times are host seconds since the call started.  Slot buffers are
+ * allocated once, for the largest mesh.  Synchronous; uses AUTO strategy.
+ *   meshes/recipes  host arrays [n_meshes]: handles, generate_ke recipes
+ *   requests        host array [n_requests], sorted by arrival_s
+ *   results         host array [n_requests]
+ *   reassembly_latency  optional host array [sum of n_reassembly]: each
+ *                   re-assembly's issue-to-completion time, request order
+ */
+typedef struct {
+    double arrival_s;     /* seconds after the start of the run */
+    int32_t mesh;         /* index into the mesh table */
+    int32_t n_reassembly; /* value-only re-assemblies after the assembly */
+    uint64_t seed;        /* element-matrix key of the request */
+    double* keep_values;  /* optional dev double [nnz]: receives the final values */
+} feasm_request;
+
+typedef struct {
+    double admitted_s, assembled_s, done_s;
+} feasm_request_result;
+
+int serve_run(const feasm_pattern* const* meshes, const int32_t* recipes, int64_t n_meshes,
+              const feasm_request* requests, int64_t n_requests, int fmt, int32_t slots,
+              int64_t hbm_budget, feasm_request_result* results, double* reassembly_latency);
+
 #ifdef __cplusplus
 }
 #endif

@@ -32,6 +32,17 @@ PP = ctypes.POINTER(ctypes.c_void_p)
 PI64 = ctypes.POINTER(ctypes.c_int64)
 PI32 = ctypes.POINTER(ctypes.c_int32)
 
+class Request(ctypes.Structure):
+    _fields_ = [("arrival_s", ctypes.c_double), ("mesh", ctypes.c_int32),
+                ("n_reassembly", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("keep_values", ctypes.c_void_p)]
+
+
+class RequestResult(ctypes.Structure):
+    _fields_ = [("admitted_s", ctypes.c_double), ("assembled_s", ctypes.c_double),
+                ("done_s", ctypes.c_double)]
+
+
 SIGNATURES = {
     "pattern_build": (INT, [P, I64, I32, I32, I64, U32, P, PP]),
     "assemble_csr": (INT, [P, P, P, INT, P]),
@@ -47,6 +58,8 @@ SIGNATURES = {
     "assemble_batch": (INT, [P, P, P, P]),
     "batch_info": (INT, [P, PI32, PI64, PI64, P]),
     "batch_free": (None, [P]),
+    "serve_run": (INT, [P, P, I64, ctypes.POINTER(Request), I64, INT, I32, I64,
+                        ctypes.POINTER(RequestResult), P]),
     "last_error": (ctypes.c_char_p, []),
 }
 

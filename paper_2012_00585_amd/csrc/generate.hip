@@ -1,14 +1,17 @@
 // Element-matrix generator for benchmarks and serving: counter-based
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and two recipes whose
 // arithmetic is exact or a fixed sequence of correctly rounded IEEE
-// operations (no fused multiply-add), so the matrices are reproducible bit
-// for bit by any implementation of the same definition.
+// operations (the library is built without FMA contraction), so the
+// matrices are reproducible bit for bit by any implementation of the same
+// definition.  Entry i = r*n + s of element e takes 32-bit word i mod 4 of
+// Philox(counter (i div 4, (e+e0) low, (e+e0) high, recipe), key (seed low,
+// seed high)), u = word * 2^-32.
 //
-//   laplacian  K_rs = 2u - 1 (r < s, mirrored), K_rr = -sum_{s != r} K_rs
-//   spd        B_ij = (((u0+u1)+u2)+u3 - 2) * sqrt(3);  K = B B^T / n + I
+//   laplacian  K_rs = 2u - 1 for r < s (mirrored); K_rr = -sum_{s != r} K_rs
+//              in increasing s
+//   spd        B_rs = (u - 1/2) * sqrt(12) (unit variance);
+//              K_rs = (sum_t B_rt B_st, t increasing) / n + [r == s]
 //
-// u = x * 2^-32 for a 32-bit Philox output x; element e uses counters
-// (entry, (e+e0) low, (e+e0) high, recipe) under key (seed low, seed high).
 // This is workload generation, not part of the assembly method.
 #include <algorithm>
 
@@ -38,56 +41,75 @@ __device__ inline void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2, u
 }
 
 constexpr double kTwoM32 = 2.3283064365386963e-10;  // 2^-32
-constexpr double kSqrt3 = 1.7320508075688772;
+constexpr double kSqrt12 = 3.4641016151377544;
 
-// One block per element; K staged in LDS.
-__global__ void __launch_bounds__(256)
-    k_gen(int kind, int64_t n_elem, int32_t n, uint32_t k0, uint32_t k1, int64_t e0,
+// One 64-lane block per element; the uniforms in LDS, the product in 4x4
+// register blocks (upper triangle of blocks, mirrored).
+__global__ void __launch_bounds__(64)
+    k_gen(int recipe, int64_t n_elem, int32_t n, uint32_t k0, uint32_t k1, int64_t e0,
           double* __restrict__ ke) {
-    extern __shared__ double sm[];
-    double* B = sm;  // [n][n]
+    extern __shared__ double B[];  // [n*n]
     const int32_t n2 = n * n;
+    const int32_t nb = (n + 3) >> 2;
     for (int64_t e = blockIdx.x; e < n_elem; e += gridDim.x) {
         const uint64_t ge = (uint64_t)(e + e0);
         double* K = ke + e * (int64_t)n2;
-        if (kind == 0) {
-            for (int32_t i = threadIdx.x; i < n2; i += blockDim.x) {
-                uint32_t c0 = (uint32_t)i, c1 = (uint32_t)ge, c2 = (uint32_t)(ge >> 32), c3 = 0;
-                philox4x32_10(c0, c1, c2, c3, k0, k1);
-                B[i] = __dsub_rn(__dmul_rn(2.0, __dmul_rn((double)c0, kTwoM32)), 1.0);
+        for (int32_t c = threadIdx.x; c * 4 < n2; c += 64) {
+            uint32_t w[4] = {(uint32_t)c, (uint32_t)ge, (uint32_t)(ge >> 32), (uint32_t)recipe};
+            philox4x32_10(w[0], w[1], w[2], w[3], k0, k1);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int32_t i = c * 4 + q;
+                if (i < n2) {
+                    const double u = (double)w[q] * kTwoM32;
+                    B[i] = recipe == 0 ? 2.0 * u - 1.0 : (u - 0.5) * kSqrt12;
+                }
             }
-            __syncthreads();
-            for (int32_t i = threadIdx.x; i < n2; i += blockDim.x) {
+        }
+        __syncthreads();
+        if (recipe == 0) {
+            for (int32_t i = threadIdx.x; i < n2; i += 64) {
                 const int32_t r = i / n, s = i - r * n;
-                if (r < s) {
-                    K[i] = B[i];
-                } else if (r > s) {
-                    K[i] = B[s * n + r];
+                if (r != s) {
+                    K[i] = r < s ? B[i] : B[s * n + r];
                 } else {
                     double acc = 0.0;
                     for (int32_t t = 0; t < n; ++t)
-                        if (t != r) acc = __dadd_rn(acc, r < t ? B[r * n + t] : B[t * n + r]);
+                        if (t != r) acc = acc + (r < t ? B[r * n + t] : B[t * n + r]);
                     K[i] = -acc;
                 }
             }
         } else {
-            for (int32_t i = threadIdx.x; i < n2; i += blockDim.x) {
-                uint32_t c0 = (uint32_t)i, c1 = (uint32_t)ge, c2 = (uint32_t)(ge >> 32), c3 = 1;
-                philox4x32_10(c0, c1, c2, c3, k0, k1);
-                double u = __dadd_rn(__dmul_rn((double)c0, kTwoM32), __dmul_rn((double)c1, kTwoM32));
-                u = __dadd_rn(u, __dmul_rn((double)c2, kTwoM32));
-                u = __dadd_rn(u, __dmul_rn((double)c3, kTwoM32));
-                B[i] = __dmul_rn(__dsub_rn(u, 2.0), kSqrt3);
-            }
-            __syncthreads();
-            for (int32_t i = threadIdx.x; i < n2; i += blockDim.x) {
-                const int32_t r = i / n, s = i - r * n;
-                double acc = 0.0;
-                for (int32_t t = 0; t < n; ++t)
-                    acc = __dadd_rn(acc, __dmul_rn(B[r * n + t], B[s * n + t]));
-                double v = __ddiv_rn(acc, (double)n);
-                if (r == s) v = __dadd_rn(v, 1.0);
-                K[i] = v;
+            const double dn = (double)n;
+            for (int32_t bi = threadIdx.x; bi < nb * nb; bi += 64) {
+                const int32_t R = bi / nb, S = bi - R * nb;
+                if (S < R) continue;
+                double acc[4][4] = {};
+                for (int32_t t = 0; t < n; ++t) {
+                    double br[4], bs[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int32_t r = 4 * R + q, s = 4 * S + q;
+                        br[q] = r < n ? B[r * n + t] : 0.0;
+                        bs[q] = s < n ? B[s * n + t] : 0.0;
+                    }
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) acc[a][b] = acc[a][b] + br[a] * bs[b];
+                }
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const int32_t r = 4 * R + a, s = 4 * S + b;
+                        if (r < n && s < n) {
+                            double v = acc[a][b] / dn;
+                            if (r == s) v = v + 1.0;
+                            K[r * n + s] = v;
+                            K[s * n + r] = v;
+                        }
+                    }
             }
         }
         __syncthreads();
@@ -105,9 +127,9 @@ extern "C" int generate_ke(int recipe, int64_t n_elem, int32_t n, uint64_t seed,
     if (n_elem < 0 || n <= 0 || elem_offset < 0) FEASM_FAIL(FEASM_EINVAL, "generate_ke: bad size");
     if ((int64_t)n * n * 8 > 64 * 1024) FEASM_FAIL(FEASM_ELIMIT, "generate_ke: n too large");
     if (n_elem == 0) return FEASM_OK;
-    const unsigned grid = (unsigned)std::min<int64_t>(n_elem, 65536);
-    k_gen<<<grid, 256, (size_t)n * n * 8, stream>>>(recipe, n_elem, n, (uint32_t)seed,
-                                                    (uint32_t)(seed >> 32), elem_offset, ke);
+    const unsigned grid = (unsigned)std::min<int64_t>(n_elem, 1 << 20);
+    k_gen<<<grid, 64, (size_t)n * n * 8, stream>>>(recipe, n_elem, n, (uint32_t)seed,
+                                                   (uint32_t)(seed >> 32), elem_offset, ke);
     FEASM_HIP(hipGetLastError());
     return FEASM_OK;
 }

@@ -1,32 +1,27 @@
-"""Serving loop: assembly and Newton-style re-assembly requests as they arrive.
+"""Serving: assembly and Newton-style re-assembly requests as they arrive.
 
 Each request names a registered mesh (whose pattern stays resident on the
 device) and asks for one assembly followed by ``n_reassembly`` value-only
 re-assemblies, each with fresh element matrices generated on the device.
-
-Continuous batching: requests are admitted into free slots as soon as the
-HBM budget allows (footprint = two element-matrix buffers + one values
-buffer); every slot has its own stream, so the work of all admitted
-requests overlaps on the GPU, and each slot issues its next iteration the
-moment its previous one completes (a Newton loop with zero solver time).
-Element matrices for iteration i+1 are generated on the slot's side stream
-while iteration i assembles (ping-pong buffers).  ``slots=1`` gives the
-one-mesh-at-a-time FIFO baseline on one stream.
+The loop itself is libfeasm's native engine (``serve_run``): continuous
+batching into stream slots under an HBM budget, each slot issuing its next
+iteration as soon as the previous one completes, element matrices for the
+next iteration generated on a side stream.  ``slots=1`` gives the
+one-mesh-at-a-time FIFO baseline on one stream.  This module marshals the
+request table and summarises the timings.
 
 Latency is host time from arrival (assembly) or issue (re-assembly) to the
-first poll that sees the completion event.
+engine's first poll that sees the completion.
 """
 from __future__ import annotations
 
-import collections
-import time
-from dataclasses import dataclass, field
+import ctypes
+from dataclasses import dataclass
 
 import numpy as np
 import torch
 
-from . import (FMT_CRAC, FMT_CSR, SCATTER_AUTO, assemble_crac, assemble_csr, generate_ke,
-               reassemble_values)
+from . import FMT_CRAC, _lib
 
 
 @dataclass
@@ -45,31 +40,18 @@ class _Mesh:
     bytes: int  # element matrices x2 + values
 
 
-@dataclass
-class _Slot:
-    stream: object
-    side: object
-    req: Request = None
-    it: int = 0
-    ke: list = field(default_factory=list)
-    values: object = None
-    done: object = None       # event of the iteration in flight
-    gen_done: list = field(default_factory=list)
-    issued: float = 0.0
-    footprint: int = 0
-
-
 def iteration_seed(seed: int, it: int) -> int:
     """64-bit generator key of iteration `it` of a request (0 = assembly)."""
     return (seed * 1000003 + it * 7919 + 1) & ((1 << 64) - 1)
 
 
 class Server:
-    def __init__(self, fmt=FMT_CRAC, slots=8, hbm_budget=None, scatter=SCATTER_AUTO,
-                 keep=()):
+    """Request server over registered meshes.  Each mesh assembles with the
+    strategy its handle is tuned to (``Pattern.tune``; AUTO = row-owned)."""
+
+    def __init__(self, fmt=FMT_CRAC, slots=8, hbm_budget=None, keep=()):
         self.fmt = fmt
         self.nslots = slots
-        self.scatter = scatter
         self.meshes = {}
         self.budget = hbm_budget
         self.keep = set(keep)        # request ids whose final values are kept
@@ -83,123 +65,79 @@ class Server:
     def footprint(self, req):
         return self.meshes[req.mesh].bytes
 
-    def _issue(self, s: _Slot, now):
-        m = self.meshes[s.req.mesh]
-        p = m.pattern
-        buf = s.it % 2
-        s.stream.wait_event(s.gen_done[buf])
-        if s.it == 0:
-            fn = assemble_csr if self.fmt == FMT_CSR else assemble_crac
-            fn(p, s.ke[buf], s.values, self.scatter, stream=s.stream)
-        else:
-            reassemble_values(p, self.fmt, s.ke[buf], s.values, self.scatter, stream=s.stream)
-        s.done = torch.cuda.Event()
-        s.done.record(s.stream)
-        s.issued = now
-        # element matrices of the next iteration go into the other buffer; its
-        # last reader (iteration it-1) completed before this one was issued
-        nxt = s.it + 1
-        if nxt <= s.req.n_reassembly:
-            ob = nxt % 2
-            generate_ke(m.recipe, p.n_elem, p.n, iteration_seed(s.req.seed, nxt), 0,
-                        out=s.ke[ob], stream=s.side)
-            ev = torch.cuda.Event()
-            ev.record(s.side)
-            s.gen_done[ob] = ev
-
-    def _admit(self, s: _Slot, req: Request, now):
-        m = self.meshes[req.mesh]
-        p = m.pattern
-        s.req = req
-        s.it = 0
-        s.footprint = m.bytes
-        s.ke = [torch.empty((p.n_elem, p.n, p.n), dtype=torch.float64, device="cuda")
-                for _ in range(2)]
-        s.values = torch.empty(p.nnz, dtype=torch.float64, device="cuda")
-        generate_ke(m.recipe, p.n_elem, p.n, iteration_seed(req.seed, 0), 0, out=s.ke[0],
-                    stream=s.side)
-        ev = torch.cuda.Event()
-        ev.record(s.side)
-        s.gen_done = [ev, None]
-        self._issue(s, now)
-
     def run(self, requests, log=None):
-        """Serve `requests` (sorted by arrival); returns latency and throughput figures."""
-        reqs = collections.deque(sorted(requests, key=lambda r: r.arrival))
-        pending = collections.deque()
-        slots = [_Slot(torch.cuda.Stream(), torch.cuda.Stream()) for _ in range(self.nslots)]
-        used = 0
-        lat_asm, lat_re, finish = [], [], {}
-        queue_wait = []
-        elements = 0
-        max_pending = 0
+        """Serve `requests` with the native engine; returns latency and throughput figures."""
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        keys = list(self.meshes)
+        index = {k: i for i, k in enumerate(keys)}
+        handles = (ctypes.c_void_p * len(keys))(*[self.meshes[k].pattern.handle.value
+                                                  for k in keys])
+        recipes = (ctypes.c_int32 * len(keys))(*[self.meshes[k].recipe for k in keys])
+        arr = (_lib.Request * len(reqs))()
+        keep = {}
+        for i, r in enumerate(reqs):
+            arr[i].arrival_s = r.arrival
+            arr[i].mesh = index[r.mesh]
+            arr[i].n_reassembly = r.n_reassembly
+            arr[i].seed = r.seed & ((1 << 64) - 1)
+            if r.rid in self.keep:
+                p = self.meshes[r.mesh].pattern
+                keep[r.rid] = torch.empty(p.nnz, dtype=torch.float64, device="cuda")
+                arr[i].keep_values = keep[r.rid].data_ptr()
+        res = (_lib.RequestResult * len(reqs))()
+        n_re = sum(r.n_reassembly for r in reqs)
+        re_lat = np.zeros(max(n_re, 1))
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        busy = 0
-        while reqs or pending or busy:
-            now = time.perf_counter() - t0
-            while reqs and reqs[0].arrival <= now:
-                pending.append(reqs.popleft())
-            max_pending = max(max_pending, len(pending))
-            # completions
-            for s in slots:
-                if s.req is None or not s.done.query():
-                    continue
-                now = time.perf_counter() - t0
-                p = self.meshes[s.req.mesh].pattern
-                elements += p.n_elem
-                if s.it == 0:
-                    lat_asm.append(now - s.req.arrival)
-                else:
-                    lat_re.append(now - s.issued)
-                if s.it < s.req.n_reassembly:
-                    s.it += 1
-                    self._issue(s, now)
-                else:
-                    if s.req.rid in self.keep:
-                        self.kept[s.req.rid] = s.values.detach().cpu().numpy()
-                    finish[s.req.rid] = now
-                    used -= s.footprint
-                    s.req = None
-                    s.ke, s.values = [], None
-                    busy -= 1
-            # admissions: FIFO, as slots and memory free up
-            for s in slots:
-                if not pending:
-                    break
-                if s.req is not None:
-                    continue
-                req = pending[0]
-                fp = self.footprint(req)
-                if self.budget is not None and used + fp > self.budget and busy > 0:
-                    break
-                pending.popleft()
-                now = time.perf_counter() - t0
-                queue_wait.append(now - req.arrival)
-                used += fp
-                busy += 1
-                self._admit(s, req, now)
-            if not busy and reqs and not pending:
-                time.sleep(max(0.0, min(1e-4, reqs[0].arrival - (time.perf_counter() - t0))))
+        _lib.check(_lib.load().serve_run(handles, recipes, len(keys), arr, len(reqs), self.fmt,
+                                         self.nslots, int(self.budget or 0), res,
+                                         re_lat.ctypes.data_as(ctypes.c_void_p)),
+                   "serve_run")
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        span = max(r.arrival for r in requests) if requests else 0.0
+        for rid, t in keep.items():
+            self.kept[rid] = t.cpu().numpy()
+        arrival = np.array([r.arrival for r in reqs])
+        admitted = np.array([x.admitted_s for x in res])
+        assembled = np.array([x.assembled_s for x in res])
+        done = np.array([x.done_s for x in res])
+        elements = sum(self.meshes[r.mesh].pattern.n_elem * (1 + r.n_reassembly) for r in reqs)
+        wall = float(done.max()) if len(reqs) else 0.0
+        span = float(arrival.max()) if len(reqs) else 0.0
+        # in-flight concurrency from admission/completion times
+        ev = sorted([(a, 1) for a in admitted] + [(d, -1) for d in done])
+        level = peak = 0
+        for _, x in ev:
+            level += x
+            peak = max(peak, level)
 
         def pct(a, q):
-            return float(np.percentile(np.asarray(a) * 1e3, q)) if a else None
+            return float(np.percentile(np.asarray(a) * 1e3, q)) if len(a) else None
 
+        lat_asm = assembled - arrival
+        wait = admitted - arrival
+        re = re_lat[:n_re]
         return {
-            "requests": len(finish),
+            "requests": len(reqs),
             "wall_s": wall,
             "arrival_span_s": span,
-            "offered_req_per_s": len(requests) / span if span > 0 else None,
-            "achieved_req_per_s": len(finish) / wall if wall > 0 else None,
+            "offered_req_per_s": len(reqs) / span if span > 0 else None,
+            "achieved_req_per_s": len(reqs) / wall if wall > 0 else None,
             "element_matrices_per_s": elements / wall if wall > 0 else None,
             "assembly_ms": {"p50": pct(lat_asm, 50), "p99": pct(lat_asm, 99),
-                            "mean": float(np.mean(lat_asm) * 1e3) if lat_asm else None},
-            "reassembly_ms": {"p50": pct(lat_re, 50), "p99": pct(lat_re, 99),
-                              "mean": float(np.mean(lat_re) * 1e3) if lat_re else None},
-            "queue_wait_ms": {"p50": pct(queue_wait, 50), "p99": pct(queue_wait, 99)},
-            "max_pending": max_pending,
+                            "mean": float(lat_asm.mean() * 1e3) if len(reqs) else None},
+            "reassembly_ms": {"p50": pct(re, 50), "p99": pct(re, 99),
+                              "mean": float(re.mean() * 1e3) if n_re else None},
+            "queue_wait_ms": {"p50": pct(wait, 50), "p99": pct(wait, 99)},
+            "max_pending": int(_max_waiting(arrival, admitted)),
+            "peak_in_flight": peak,
             "slots": self.nslots,
         }
+
+
+def _max_waiting(arrival, admitted):
+    """Largest number of requests that had arrived but were not yet admitted."""
+    ev = sorted([(a, 1) for a in arrival] + [(b, -1) for b in admitted])
+    level = peak = 0
+    for _, x in ev:
+        level += x
+        peak = max(peak, level)
+    return peak
