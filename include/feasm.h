@@ -188,6 +188,17 @@ int pattern_colouring(const feasm_pattern* p, const int64_t** colour_ptr,
  *                                   batch, 8 or 16
  *   FEASM_TUNE_STRATEGY             the strategy FEASM_SCATTER_AUTO resolves to
  *                                   for this handle (and in batches)
+ *   FEASM_TUNE_OWNER_FLAT           row-owned strategy: one node row per
+ *                                   wavefront, the element rows of a batch of 8
+ *                                   or 16 entries read as one flat array; 0 =
+ *                                   auto (8 if no node has more than 8 incident
+ *                                   entries, else 16), -1 = off.  Compiled for
+ *                                   8-node hexes and 10-node tets with 3 DOFs
+ *                                   per node; other shapes keep the launch the
+ *                                   settings above choose
+ *   FEASM_TUNE_OWNER_PREFETCH       flat batches, rows longer than one batch:
+ *                                   1 = issue the next batch's loads before the
+ *                                   current batch is added (more registers)
  * Returns EINVAL for an unknown key or value.
  */
 enum {
@@ -195,7 +206,9 @@ enum {
     FEASM_TUNE_THREADS_PER_ELEM = 2,
     FEASM_TUNE_OWNER_ROWS = 3,
     FEASM_TUNE_OWNER_BATCH = 4,
-    FEASM_TUNE_STRATEGY = 5
+    FEASM_TUNE_STRATEGY = 5,
+    FEASM_TUNE_OWNER_FLAT = 6,
+    FEASM_TUNE_OWNER_PREFETCH = 7
 };
 int pattern_tune(feasm_pattern* p, int key, int64_t value);
 

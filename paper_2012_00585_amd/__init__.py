@@ -34,6 +34,8 @@ TUNE_THREADS_PER_ELEM = 2
 TUNE_OWNER_ROWS = 3
 TUNE_OWNER_BATCH = 4
 TUNE_STRATEGY = 5
+TUNE_OWNER_FLAT = 6
+TUNE_OWNER_PREFETCH = 7
 
 _HIP_D2D = 3  # hipMemcpyDeviceToDevice
 

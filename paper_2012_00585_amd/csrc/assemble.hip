@@ -57,6 +57,12 @@ __global__ void __launch_bounds__(64) k_owner(OwnArgs A) {
     owner_tiles<FMT, G, J, B>(A, first, last, lds_d);
 }
 
+template <int FMT, int D, int N, int B, int MODE>
+__global__ void __launch_bounds__(64) k_owner_pipe(OwnArgs A) {
+    extern __shared__ double lds_d[];
+    owner_pipe_row<FMT, D, N, B, MODE>(A, xcd_block(blockIdx.x, gridDim.x), lds_d);
+}
+
 template <int FMT, int R, int J, int B>
 __global__ void __launch_bounds__(64) k_owner_rows(OwnArgs A) {
     extern __shared__ double lds_d[];
@@ -94,7 +100,8 @@ OwnShape owner_shape(const feasm_pattern* p, int fmt) {
         const int j = (int)ceil_div(dn, g);
         const int jj = j <= 1 ? 1 : j <= 2 ? 2 : j <= 4 ? 4 : j <= 8 ? 8 : 16;
         const int b = jj <= 2 ? 8 : jj == 4 ? 4 : jj == 8 ? 2 : 1;
-        const int64_t idx = (fmt == kCSR) ? (int64_t)p->d * p->max_deg : 2 * (int64_t)p->max_deg + 2;
+        const int64_t idx = fmt == kMap ? 0
+                            : fmt == kCSR ? (int64_t)p->d * p->max_deg : 2 * (int64_t)p->max_deg + 2;
         const int64_t bytes = (int64_t)p->d * p->d * p->max_deg * 8 + idx * 4 + (int64_t)b * p->k * 4;
         const int64_t gb = ceil_div(bytes, 8) * 8;
         if (gb * (64 / g) <= 64 * 1024) return {g, jj, b, (int32_t)gb};
@@ -129,9 +136,33 @@ int launch_owner_f(const feasm_pattern* p, OwnArgs& A, hipStream_t s) {
     const OwnShape sh = owner_shape(p, FMT);
     if (sh.g == 0)
         FEASM_FAIL(FEASM_ELIMIT, "row-owned assembly: node rows too long for the LDS accumulator");
-    A.idx_ints = (FMT == kCSR) ? p->d * p->max_deg : 2 * p->max_deg + 2;
+    A.idx_ints = FMT == kMap ? 0 : FMT == kCSR ? p->d * p->max_deg : 2 * p->max_deg + 2;
     A.acc_doubles = p->d * p->d * p->max_deg;
     A.group_bytes = sh.group_bytes;
+    // Flat, pipelined batches (tuned): one node row per wavefront, B entries
+    // per batch, for the element shapes they are compiled for.
+    // By default (setting 0) they are used wherever they are compiled, with
+    // 8 entries per batch where no row is longer, else 16.
+    if (p->tune_owner_flat >= 0 && sh.g == 64) {
+        const int B = p->tune_owner_flat > 0 ? p->tune_owner_flat : p->max_inc <= 8 ? 8 : 16;
+        const size_t lds = (size_t)A.group_bytes + (size_t)2 * B * p->k * 4;
+        if (lds <= 64 * 1024) {
+            const unsigned blocks = (unsigned)p->n_nodes;
+#define FEASM_PIPE(DD, NN, BB)                                                          \
+    if (p->d == DD && p->n == NN && B == BB) {                                         \
+        if (p->max_inc <= BB)                                                          \
+            k_owner_pipe<FMT, DD, NN, BB, 0><<<blocks, 64, lds, s>>>(A);               \
+        else if (p->tune_owner_prefetch)                                               \
+            k_owner_pipe<FMT, DD, NN, BB, 2><<<blocks, 64, lds, s>>>(A);               \
+        else                                                                           \
+            k_owner_pipe<FMT, DD, NN, BB, 1><<<blocks, 64, lds, s>>>(A);               \
+        FEASM_HIP(hipGetLastError());                                                   \
+        return FEASM_OK;                                                                \
+    }
+            FEASM_PIPE(3, 24, 8) FEASM_PIPE(3, 24, 16) FEASM_PIPE(3, 30, 8) FEASM_PIPE(3, 30, 16)
+#undef FEASM_PIPE
+        }
+    }
     // Default: two node rows per wavefront while a row's accumulator is small
     // enough that occupancy is not bound by LDS.
     int rows = p->tune_owner_rows;
@@ -170,8 +201,15 @@ bool owner_fits(const feasm_pattern* p, int fmt) {
     return (int64_t)p->d * p->n <= 1024 && owner_shape(p, fmt).g != 0;
 }
 
+// Records every row-owned lookup (owner_map_node) for one node per block.
+template <int FMT>
+__global__ void __launch_bounds__(64) k_owner_map(OwnArgs A, int32_t* out) {
+    extern __shared__ int32_t sidx[];
+    for (int64_t v = blockIdx.x; v < A.n_nodes; v += gridDim.x) owner_map_node<FMT>(A, v, sidx, out);
+}
+
 int launch_owner(const feasm_pattern* p, int fmt, const double* ke, double* values, bool accumulate,
-                 hipStream_t s) {
+                 hipStream_t s, const int32_t* map = nullptr) {
     if ((int64_t)p->d * p->n > 1024)
         FEASM_FAIL(FEASM_ELIMIT, "row-owned assembly supports d * n <= 1024");
     OwnArgs A{};
@@ -191,7 +229,35 @@ int launch_owner(const feasm_pattern* p, int fmt, const double* ke, double* valu
     A.values = values;
     A.n_nodes = p->n_nodes;
     A.accumulate = accumulate ? 1 : 0;
+    A.node_ptr = p->node_ptr;
+    A.map = map;
+    if (map) return launch_owner_f<kMap>(p, A, s);
     return fmt == kCSR ? launch_owner_f<kCSR>(p, A, s) : launch_owner_f<kCRAC>(p, A, s);
+}
+
+// Builds the row-owned lookup record of a handle (same for both formats).
+int build_owner_map(feasm_pattern* p, int fmt, hipStream_t s) {
+    OwnArgs A{};
+    A.conn = p->conn;
+    A.k = p->k;
+    A.d = p->d;
+    A.n = p->n;
+    A.inc_ptr = p->inc_ptr;
+    A.inc_elem = p->inc_elem;
+    A.row_ptr = p->row_ptr;
+    A.col_idx = p->col_idx;
+    A.crac_row_ptr = p->crac_row_ptr;
+    A.ca = p->ca;
+    A.n_nodes = p->n_nodes;
+    const size_t lds = sizeof(int32_t) * (size_t)std::max<int64_t>(
+        (int64_t)p->d * p->max_deg, 2 * (int64_t)p->max_deg + 2);
+    const unsigned grid = (unsigned)std::min<int64_t>(p->n_nodes, 1 << 20);
+    if (fmt == kCSR)
+        k_owner_map<kCSR><<<grid, 64, lds, s>>>(A, p->owner_map);
+    else
+        k_owner_map<kCRAC><<<grid, 64, lds, s>>>(A, p->owner_map);
+    FEASM_HIP(hipGetLastError());
+    return FEASM_OK;
 }
 
 // Threads per element and values per thread, by element-matrix size.
@@ -237,7 +303,8 @@ int launch(int fmt, bool atomic, const AsmArgs& A, const Shape& sh, hipStream_t 
 }
 
 int assemble_impl(const feasm_pattern* p, int fmt, const double* ke, double* values, int scatter,
-                  const int32_t* cache, int32_t* cache_out, hipStream_t s, const char* who) {
+                  const int32_t* cache, int32_t* cache_out, hipStream_t s, const char* who,
+                  const int32_t* owner_map = nullptr) {
     if (!p) FEASM_FAIL(FEASM_EINVAL, std::string(who) + ": null handle");
     if (!ke || !values) FEASM_FAIL(FEASM_EINVAL, std::string(who) + ": ke or values is NULL");
     if (fmt == kCSR && !(p->flags & FEASM_BUILD_CSR))
@@ -255,7 +322,8 @@ int assemble_impl(const feasm_pattern* p, int fmt, const double* ke, double* val
     if (scatter != FEASM_SCATTER_ATOMIC && scatter != FEASM_SCATTER_COLOURED &&
         scatter != FEASM_SCATTER_OWNER)
         FEASM_FAIL(FEASM_EINVAL, std::string(who) + ": unknown scatter strategy");
-    if (scatter == FEASM_SCATTER_OWNER) return launch_owner(p, fmt, ke, values, accumulate, s);
+    if (scatter == FEASM_SCATTER_OWNER)
+        return launch_owner(p, fmt, ke, values, accumulate, s, owner_map);
     if (scatter == FEASM_SCATTER_COLOURED && !(p->flags & FEASM_BUILD_COLOUR))
         FEASM_FAIL(FEASM_EINVAL,
                    std::string(who) + ": coloured scatter needs a handle built with colouring");
@@ -307,6 +375,12 @@ int assemble_on_stream(const feasm_pattern* p, int fmt, const double* ke, double
     return assemble_impl(p, fmt, ke, values, scatter, nullptr, nullptr, s, "assemble_batch");
 }
 
+void release_owner_map(feasm_pattern* p) {
+    if (p->owner_map) (void)hipFree(p->owner_map);
+    p->owner_map = nullptr;
+    p->owner_map_valid = false;
+}
+
 void release_cache(feasm_pattern* p) {
     if (p->cache) {
         if (p->cache->base) (void)hipFree(p->cache->base);
@@ -350,9 +424,24 @@ extern "C" int reassemble_values(feasm_pattern* p, int fmt, const double* ke, do
             strategy = owner_fits(p, fmt) ? FEASM_SCATTER_OWNER : FEASM_SCATTER_ATOMIC;
         scatter = strategy | (scatter & FEASM_ACCUMULATE);
     }
-    if (strategy == FEASM_SCATTER_OWNER || strategy == FEASM_SCATTER_AUTO)
+    if (strategy == FEASM_SCATTER_OWNER || strategy == FEASM_SCATTER_AUTO) {
+        if (!p->owner_map_valid) {
+            if (!p->owner_map) {
+                const size_t bytes = sizeof(int32_t) * (size_t)p->n_elem * p->k * p->k;
+                if (hipMalloc((void**)&p->owner_map, bytes) != hipSuccess) {
+                    p->owner_map = nullptr;
+                    FEASM_FAIL(FEASM_ENOMEM, "reassemble_values: cannot allocate lookup record");
+                }
+            }
+            const int rc = build_owner_map(p, fmt, stream);
+            if (rc != FEASM_OK) return rc;
+            // the record is complete before any call, on any stream, may read it
+            FEASM_HIP(hipStreamSynchronize(stream));
+            p->owner_map_valid = true;
+        }
         return assemble_impl(p, fmt, ke, values, scatter, nullptr, nullptr, stream,
-                             "reassemble_values");
+                             "reassemble_values", p->owner_map);
+    }
     if (p->cache && p->cache->valid && p->cache->fmt == fmt)
         return assemble_impl(p, fmt, ke, values, scatter, p->cache->base, nullptr, stream,
                              "reassemble_values");
@@ -403,6 +492,18 @@ extern "C" int pattern_tune(feasm_pattern* p, int key, int64_t value) {
         if (value != 0 && value != 8 && value != 16)
             FEASM_FAIL(FEASM_EINVAL, "pattern_tune: owner batch must be 8 or 16");
         p->tune_owner_batch = (int32_t)value;
+        return FEASM_OK;
+    }
+    if (key == FEASM_TUNE_OWNER_PREFETCH) {
+        if (value != 0 && value != 1)
+            FEASM_FAIL(FEASM_EINVAL, "pattern_tune: owner prefetch must be 0 or 1");
+        p->tune_owner_prefetch = (int32_t)value;
+        return FEASM_OK;
+    }
+    if (key == FEASM_TUNE_OWNER_FLAT) {
+        if (value != -1 && value != 0 && value != 8 && value != 16)
+            FEASM_FAIL(FEASM_EINVAL, "pattern_tune: flat batch must be -1 (off), 0 (auto), 8 or 16");
+        p->tune_owner_flat = (int32_t)value;
         return FEASM_OK;
     }
     if (key == FEASM_TUNE_STRATEGY) {

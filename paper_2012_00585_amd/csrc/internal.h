@@ -39,6 +39,9 @@ struct OffsetCache;  // value-only re-assembly lookup cache (assemble.hip)
 
 }  // namespace feasm
 
+// Entries of padding after the incidence array (zeros).
+constexpr int kIncPad = 64;
+
 struct feasm_pattern {
     int device = 0;
     int64_t n_elem = 0;
@@ -81,6 +84,8 @@ struct feasm_pattern {
     int32_t* elem_colour = nullptr;   // dev [n_elem]
 
     feasm::OffsetCache* cache = nullptr;
+    int32_t* owner_map = nullptr;  // dev [n_elem*k][k]: row-owned lookup record
+    bool owner_map_valid = false;
 
     // tuning (0 = library default)
     int32_t tune_owner_blocks_per_cu = 0;  // >0: persistent row-owned grid of this size per CU
@@ -88,6 +93,8 @@ struct feasm_pattern {
     int32_t tune_owner_rows = 0;           // >1: node rows per wavefront (row-owned, large elements)
     int32_t tune_owner_batch = 0;          // incidence entries loaded per batch (8 or 16)
     int32_t tune_strategy = 0;             // what FEASM_SCATTER_AUTO resolves to (0: row-owned)
+    int32_t tune_owner_flat = 0;           // flat batches: -1 off, 0 auto, else entries per batch
+    int32_t tune_owner_prefetch = 0;       // flat batches: issue the next batch early
 };
 
 namespace feasm {
@@ -111,6 +118,7 @@ int assemble_on_stream(const feasm_pattern* p, int fmt, const double* ke, double
 // Free every device array of the handle.
 void release_pattern(feasm_pattern* p);
 void release_cache(feasm_pattern* p);
+void release_owner_map(feasm_pattern* p);
 
 // XCD-aware block order: hardware dispatches workgroup b to XCD b % 8.
 // Maps it to a logical index so that each XCD processes one contiguous range.

@@ -362,7 +362,10 @@ int build(feasm_pattern* p, const int32_t* conn_in, hipStream_t s) {
     const int64_t scratch_n = scan_scratch_elems(nn + 1);
     TRY(tmp.alloc(&scratch, scratch_n));
     TRY(dalloc(&p->inc_ptr, nn + 1));
-    TRY(dalloc(&p->inc_q, ek));
+    // padded so that a row's incidence entries can be read in whole
+    // batches of up to kIncPad entries with scalar loads
+    TRY(dalloc(&p->inc_q, ek + kIncPad));
+    FEASM_HIP(hipMemsetAsync(p->inc_q + ek, 0, sizeof(int32_t) * kIncPad, s));
     TRY(exclusive_scan<int32_t>(inc_count, nn, p->inc_ptr, scratch, s));
     k_fill_incidence<<<grid_for(ek, 256), 256, 0, s>>>(p->conn, ek, p->inc_ptr, cursor, p->inc_q);
     FEASM_HIP(hipGetLastError());
@@ -461,6 +464,7 @@ void release_pattern(feasm_pattern* p) {
     for (void* a : arrs)
         if (a) (void)hipFree(a);
     release_cache(p);
+    release_owner_map(p);
 }
 
 }  // namespace feasm

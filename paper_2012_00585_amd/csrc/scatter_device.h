@@ -9,7 +9,9 @@ namespace scatter {
 
 constexpr int kBlock = 256;
 
-enum { kCSR = 0, kCRAC = 1 };
+// kMap: the row-owned kernels with their lookups replaced by a record of
+// them (value-only re-assembly; positions are the same for both formats).
+enum { kCSR = 0, kCRAC = 1, kMap = 2 };
 
 struct AsmArgs {
     const int32_t* conn;
@@ -222,6 +224,9 @@ struct OwnArgs {
     int32_t group_bytes;  // per group LDS bytes (8-byte multiple)
     int32_t accumulate;
     int32_t persistent;   // 1: grid smaller than the tile count, blocks loop
+    const int64_t* node_ptr;  // kMap: row starts and lengths from the node pattern
+    const int32_t* map;       // kMap: per incidence entry t, map[t*k + b] = offset of
+                              // element node b's first column in the owned row
 };
 
 template <int FMT>
@@ -310,7 +315,11 @@ __device__ inline void owner_tiles(const OwnArgs& A, int64_t first, int64_t last
             const int32_t R = d * (int32_t)v;
             ib = A.inc_ptr[v];
             L = (int32_t)(A.inc_ptr[v + 1] - ib);
-            if (FMT == kCSR) {
+            if (FMT == kMap) {
+                const int64_t nb = A.node_ptr[v];
+                rs = (int32_t)((int64_t)d * d * nb);
+                ncols = (int32_t)(d * (A.node_ptr[v + 1] - nb));
+            } else if (FMT == kCSR) {
                 rs = A.row_ptr[R];
                 ncols = A.row_ptr[R + 1] - rs;
             } else {
@@ -330,7 +339,8 @@ __device__ inline void owner_tiles(const OwnArgs& A, int64_t first, int64_t last
         }
         if (active) {
             const int32_t R = d * (int32_t)v;
-            if (FMT == kCSR) {
+            if (FMT == kMap) {
+            } else if (FMT == kCSR) {
                 for (int x = l; x < ncols; x += G) sidx[x] = A.col_idx[rs + x];
             } else if (npairs > 0) {
                 const int32_t pb = A.crac_row_ptr[R];
@@ -360,7 +370,9 @@ __device__ inline void owner_tiles(const OwnArgs& A, int64_t first, int64_t last
             if (active) {
                 int tb = tb0, b = b0;
                 for (int w = l; w < B * k; w += G) {
-                    if (t0 + tb < L) {
+                    if (FMT == kMap && t0 + tb < L) {
+                        scol[w] = A.map[(ib + t0 + tb) * k + b];
+                    } else if (t0 + tb < L) {
                         const int64_t e = A.inc_elem[ib + t0 + tb];
                         const int32_t col = d * A.conn[e * k + b];
                         scol[w] = row_lookup<FMT>(sidx, ncols, npairs, rs, col);
@@ -438,7 +450,11 @@ __device__ inline void owner_rows_tile(const OwnArgs& A, int64_t blk, double* ld
         npairs[r] = 0;
         if (r < nrows) {
             const int32_t Rw = d * (int32_t)(v0 + r);
-            if (FMT == kCSR) {
+            if (FMT == kMap) {
+                const int64_t nb = A.node_ptr[v0 + r];
+                rs[r] = (int32_t)((int64_t)d * d * nb);
+                ncols[r] = (int32_t)(d * (A.node_ptr[v0 + r + 1] - nb));
+            } else if (FMT == kCSR) {
                 rs[r] = A.row_ptr[Rw];
                 ncols[r] = A.row_ptr[Rw + 1] - rs[r];
             } else {
@@ -454,7 +470,8 @@ __device__ inline void owner_rows_tile(const OwnArgs& A, int64_t blk, double* ld
         double* acc = reinterpret_cast<double*>(reinterpret_cast<char*>(lds_d) + r * A.group_bytes);
         int32_t* sidx = reinterpret_cast<int32_t*>(acc + A.acc_doubles);
         if (r < nrows) {
-            if (FMT == kCSR) {
+            if (FMT == kMap) {
+            } else if (FMT == kCSR) {
                 for (int x = l; x < ncols[r]; x += 64) sidx[x] = A.col_idx[rs[r] + x];
             } else if (npairs[r] > 0) {
                 const int32_t pb = A.crac_row_ptr[d * (int32_t)(v0 + r)];
@@ -483,7 +500,9 @@ __device__ inline void owner_rows_tile(const OwnArgs& A, int64_t blk, double* ld
             int tb = tb0, b = b0;
             for (int w = l; w < B * k; w += 64) {
                 const int64_t t = bound[0] + t0 + tb;
-                if (t0 + tb < T) {
+                if (FMT == kMap && t0 + tb < T) {
+                    scol[w] = A.map[t * k + b];
+                } else if (t0 + tb < T) {
                     int r = 0;
 #pragma unroll
                     for (int rr = 1; rr < R; ++rr) r += (t >= bound[rr]);
@@ -549,6 +568,222 @@ __device__ inline void owner_rows_tile(const OwnArgs& A, int64_t blk, double* ld
     }
 }
 
+// One wavefront owns one node row and walks its incidence entries in batches
+// of B.  The element rows of a batch are read as one flat array: value u of
+// lane l is value l + 64u of the batch, so every load instruction is full
+// and no register holds padding (V = ceil(B*D*N/64) values per lane).  The
+// element shape is fixed at compile time, so the lane indexing reduces to
+// constants.  Since D*N >= 64, the lanes of one instruction cover at most two
+// consecutive entries, lo = 64u/(D*N) and lo + 1, whose element numbers come
+// from scalar loads.  The adds of the two entries are issued as two
+// instructions, the lower entry first, so every value still receives its
+// contributions in element order.
+//
+// A batch's index loads (column nodes, or the recorded offsets) are issued
+// before its element-row loads, and the first batch's loads before the row's
+// own index words are staged, so a wavefront waits for memory about once per
+// batch rather than once per dependent load.  The incidence array is padded by kIncPad entries, which lets a batch's
+// element numbers be read with unconditional scalar loads.
+// The lane id, hidden from the optimiser so that per-lane index arithmetic is
+// recomputed where it is used instead of being kept live across a loop.
+__device__ inline int opaque_lane() {
+    int l = (int)threadIdx.x;
+    asm volatile("" : "+v"(l));
+    return l;
+}
+
+template <int FMT, int D, int N, int B>
+struct PipeBatch {
+    static constexpr int DN = D * N, K = N / D, V = (B * DN + 63) / 64, KB = B * K, W = (KB + 63) / 64;
+    double val[V];
+    int32_t ix[W];
+};
+
+template <int FMT, int D, int N, int B, bool OPAQUE>
+__device__ inline void pipe_issue(const OwnArgs& A, int64_t tbeg, int64_t T, int64_t t0,
+                                  PipeBatch<FMT, D, N, B>& bt) {
+    using P = PipeBatch<FMT, D, N, B>;
+    constexpr int DN = P::DN, K = P::K, V = P::V, KB = P::KB, W = P::W;
+    const int l = OPAQUE ? opaque_lane() : (int)threadIdx.x;
+    int32_t qs[B];
+#pragma unroll
+    for (int tb = 0; tb < B; ++tb) qs[tb] = A.inc_q[tbeg + t0 + tb];
+    // index loads first: their waits then leave the element rows in flight
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+        const int w = l + 64 * i, tb = w / K, b = w % K;
+        bt.ix[i] = -1;
+        if (w < KB && t0 + tb < T) {
+            if (FMT == kMap) {
+                bt.ix[i] = A.map[(tbeg + t0 + tb) * K + b];
+            } else {
+                int32_t q = qs[0];
+#pragma unroll
+                for (int x = 1; x < B; ++x)
+                    if (tb == x) q = qs[x];
+                bt.ix[i] = A.conn[(int64_t)(q / K) * K + b];
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+        const int lo = (64 * u) / DN, split = (lo + 1) * DN - 64 * u;
+        const int hi = l >= split;
+        const int j = l + 64 * u - (lo + hi) * DN;
+        const int32_t q = (hi && lo + 1 < B) ? qs[lo + 1 < B ? lo + 1 : lo] : qs[lo];
+        bt.val[u] = 0.0;
+        if (lo + hi < B && t0 + lo + hi < T)
+            bt.val[u] = __builtin_nontemporal_load(A.ke + (int64_t)q * DN + j);
+    }
+}
+
+template <int FMT, int D, int N, int B, bool OPAQUE>
+__device__ inline void pipe_consume(const OwnArgs& A, int64_t T, int64_t t0, int32_t rs, int32_t ncols,
+                                    int32_t npairs, const PipeBatch<FMT, D, N, B>& bt, double* acc,
+                                    const int32_t* sidx, int32_t* scol) {
+    using P = PipeBatch<FMT, D, N, B>;
+    constexpr int DN = P::DN, K = P::K, V = P::V, KB = P::KB, W = P::W;
+    const int l = OPAQUE ? opaque_lane() : (int)threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+        const int w = l + 64 * i, tb = w / K;
+        if (w < KB && t0 + tb < T)
+            scol[w] = FMT == kMap ? bt.ix[i] : row_lookup<FMT>(sidx, ncols, npairs, rs, D * bt.ix[i]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+        const int lo = (64 * u) / DN, split = (lo + 1) * DN - 64 * u;
+        if (t0 + lo < T) {
+            const int hi = l >= split;
+            const int j = l + 64 * u - (lo + hi) * DN;
+            const int c1 = j / N, s = j % N, b = s / D, c = s % D;
+            const bool valid = lo + hi < B && t0 + lo + hi < T;
+            int32_t off = -1;
+            if (valid) off = scol[(lo + hi) * K + b];
+            double* dst = acc + c1 * ncols + off + c;
+            if (valid && off >= 0 && !hi) atomicAdd(dst, bt.val[u]);
+            if (split < 64) {
+                if (valid && off >= 0 && hi) atomicAdd(dst, bt.val[u]);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// MODE 0: every row has at most B entries (one batch, no loop); 1: batches
+// one after another; 2: the next batch is issued before the current one is
+// added (two batches of registers).
+template <int FMT, int D, int N, int B, int MODE>
+__device__ inline void owner_pipe_row(const OwnArgs& A, int64_t v, double* lds_d) {
+    static_assert(D * N >= 64 && N % D == 0 && B <= kIncPad, "pipelined rows need D*N >= 64");
+    using P = PipeBatch<FMT, D, N, B>;
+    // in loops, per-lane index arithmetic is recomputed rather than kept live
+    constexpr bool OPQ = MODE != 0;
+    constexpr int SI = 4;  // index words per lane staged ahead of the first batch
+    const int l = threadIdx.x;
+    double* acc = lds_d;
+    int32_t* sidx = reinterpret_cast<int32_t*>(acc + A.acc_doubles);
+    int32_t* scol0 = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(lds_d) + A.group_bytes);
+    int32_t* scol1 = scol0 + P::KB;
+
+    const int64_t tbeg = A.inc_ptr[v], T = A.inc_ptr[v + 1] - tbeg;
+    const int32_t Rw = D * (int32_t)v;
+    int32_t rs = 0, ncols = 0, npairs = 0, nidx = 0;
+    const int32_t* isrc = nullptr;
+    if (FMT == kMap) {
+        const int64_t nb = A.node_ptr[v];
+        rs = (int32_t)((int64_t)D * D * nb);
+        ncols = (int32_t)(D * (A.node_ptr[v + 1] - nb));
+    } else if (FMT == kCSR) {
+        rs = A.row_ptr[Rw];
+        ncols = A.row_ptr[Rw + 1] - rs;
+        isrc = A.col_idx + rs;
+        nidx = ncols;
+    } else {
+        const int32_t pb = A.crac_row_ptr[Rw], pe = A.crac_row_ptr[Rw + 1];
+        npairs = (pe - pb) >> 1;
+        rs = npairs > 0 ? A.ca[pb + 1] : 0;
+        ncols = npairs > 0 ? A.ca[pe + 1] - rs : 0;
+        isrc = A.ca + pb;
+        nidx = npairs > 0 ? 2 * npairs + 2 : 0;
+    }
+    // the row's index words: loaded first, stored to LDS once the first
+    // batch's loads are in flight
+    int32_t sreg[SI];
+#pragma unroll
+    for (int i = 0; i < SI; ++i) {
+        const int x = l + 64 * i;
+        sreg[i] = x < nidx ? isrc[x] : 0;
+    }
+    P b0;
+    if (T > 0) pipe_issue<FMT, D, N, B, OPQ>(A, tbeg, T, 0, b0);
+#pragma unroll
+    for (int i = 0; i < SI; ++i) {
+        const int x = l + 64 * i;
+        if (x < nidx) sidx[x] = sreg[i];
+    }
+    for (int x = l + 64 * SI; x < nidx; x += 64) sidx[x] = isrc[x];
+    for (int x = l; x < D * ncols; x += 64) acc[x] = 0.0;
+    __syncthreads();
+    if (MODE == 2) {
+        P b1;
+        for (int64_t t0 = 0; t0 < T; t0 += 2 * B) {
+            if (t0 + B < T) pipe_issue<FMT, D, N, B, OPQ>(A, tbeg, T, t0 + B, b1);
+            pipe_consume<FMT, D, N, B, OPQ>(A, T, t0, rs, ncols, npairs, b0, acc, sidx, scol0);
+            if (t0 + B >= T) break;
+            if (t0 + 2 * B < T) pipe_issue<FMT, D, N, B, OPQ>(A, tbeg, T, t0 + 2 * B, b0);
+            pipe_consume<FMT, D, N, B, OPQ>(A, T, t0 + B, rs, ncols, npairs, b1, acc, sidx, scol1);
+        }
+    } else {
+        if (T > 0) pipe_consume<FMT, D, N, B, OPQ>(A, T, 0, rs, ncols, npairs, b0, acc, sidx, scol0);
+        if (MODE == 1) {
+            for (int64_t t0 = B; t0 < T; t0 += B) {
+                pipe_issue<FMT, D, N, B, OPQ>(A, tbeg, T, t0, b0);
+                pipe_consume<FMT, D, N, B, OPQ>(A, T, t0, rs, ncols, npairs, b0, acc, sidx, scol0);
+            }
+        }
+    }
+    double* out = A.values + rs;
+    if (A.accumulate)
+        for (int x = l; x < D * ncols; x += 64) out[x] += acc[x];
+    else
+        for (int x = l; x < D * ncols; x += 64) out[x] = acc[x];
+}
+
+// Records, for every incidence entry t of node v and every element node b,
+// the offset of b's first column inside v's rows (the lookups of the
+// row-owned kernels, done once for value-only re-assembly).  One 64-lane
+// block per node; FMT picks the CSR or CRAC search, as in owner_tiles.
+template <int FMT>
+__device__ inline void owner_map_node(const OwnArgs& A, int64_t v, int32_t* sidx, int32_t* out) {
+    const int l = threadIdx.x;
+    const int32_t k = A.k, d = A.d;
+    const int32_t R = d * (int32_t)v;
+    int32_t rs = 0, ncols = 0, npairs = 0;
+    if (FMT == kCSR) {
+        rs = A.row_ptr[R];
+        ncols = A.row_ptr[R + 1] - rs;
+        for (int x = l; x < ncols; x += 64) sidx[x] = A.col_idx[rs + x];
+    } else {
+        const int32_t pb = A.crac_row_ptr[R], pe = A.crac_row_ptr[R + 1];
+        npairs = (pe - pb) >> 1;
+        if (npairs > 0) {
+            rs = A.ca[pb + 1];
+            ncols = A.ca[pe + 1] - rs;
+            for (int x = l; x < 2 * npairs + 2; x += 64) sidx[x] = A.ca[pb + x];
+        }
+    }
+    __syncthreads();
+    const int64_t ib = A.inc_ptr[v], ie = A.inc_ptr[v + 1];
+    for (int64_t w = ib * k + l; w < ie * k; w += 64) {
+        const int64_t t = w / k;
+        const int32_t b = (int32_t)(w - t * k);
+        const int32_t col = d * A.conn[(int64_t)A.inc_elem[t] * k + b];
+        out[w] = row_lookup<FMT>(sidx, ncols, npairs, rs, col);
+    }
+    __syncthreads();
+}
 
 }  // namespace scatter
 }  // namespace feasm

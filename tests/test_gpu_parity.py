@@ -312,6 +312,7 @@ def test_owner_launch_shapes_bit_exact(feasm, orc, mesh, rows, batch):
     rp, ci = orc.pattern(conn, d, nn)
     ov, _ = orc.assemble(conn, d, ke, rp, ci)
     ke_d = torch.from_numpy(ke).to(dev)
+    p.tune(feasm.TUNE_OWNER_FLAT, -1)  # the row-batched kernels, not the flat ones
     for bpc in (0, 3):
         p.tune(feasm.TUNE_OWNER_ROWS, rows)
         p.tune(feasm.TUNE_OWNER_BATCH, batch)
@@ -319,6 +320,40 @@ def test_owner_launch_shapes_bit_exact(feasm, orc, mesh, rows, batch):
         for fn in (feasm.assemble_csr, feasm.assemble_crac):
             v = _np(fn(p, ke_d, scatter=feasm.SCATTER_OWNER))
             assert (v == ov).all(), (fn.__name__, bpc)
+    p.free()
+
+
+@pytest.mark.parametrize("mesh", ["hex7_d3", "tet3perm_d3", "q8quad2_d1", "hex4_d2"])
+def test_owner_flat_batches_bit_exact(feasm, orc, mesh):
+    """Flat batches keep element order in every value, so all launch shapes
+    give the oracle's values bit for bit, for assembly and re-assembly.
+    The flat kernels are compiled for 8-node hexes and 10-node tets with 3
+    DOFs per node; on the other meshes the setting must fall back."""
+    make = {"hex7_d3": (lambda: meshes.hex_mesh(7), 3),
+            "tet3perm_d3": (lambda: meshes.tet10_mesh(3, perm_seed=1), 3),
+            "q8quad2_d1": (lambda: meshes.qp_quad_mesh(2, 8), 1),
+            "hex4_d2": (lambda: meshes.hex_mesh(4), 2)}[mesh]
+    (conn, nn), d = make[0](), make[1]
+    E, k = conn.shape
+    ke = matrices.ke_spd(E, k * d, seed=9)
+    dev = torch.device("cuda:0")
+    p = feasm.pattern_build(torch.from_numpy(conn).to(dev), d, nn)
+    rp, ci = orc.pattern(conn, d, nn)
+    ov, _ = orc.assemble(conn, d, ke, rp, ci)
+    ke_d = torch.from_numpy(ke).to(dev)
+    for rows, prefetch in ((1, 0), (2, 1), (4, 0)):
+        for flat in (0, 8, 16):
+            say(f"[owner flat] {mesh} rows={rows} flat={flat} prefetch={prefetch}")
+            p.tune(feasm.TUNE_OWNER_ROWS, rows)
+            p.tune(feasm.TUNE_OWNER_FLAT, flat)
+            p.tune(feasm.TUNE_OWNER_PREFETCH, prefetch)
+            for fn in (feasm.assemble_csr, feasm.assemble_crac):
+                v = _np(fn(p, ke_d, scatter=feasm.SCATTER_OWNER))
+                assert (v == ov).all(), (fn.__name__, rows, flat)
+            v = _np(feasm.reassemble_values(p, feasm.FMT_CRAC, ke_d, scatter=feasm.SCATTER_OWNER))
+            assert (v == ov).all(), ("reassemble", rows, flat, prefetch)
+    with pytest.raises(feasm.FeasmError):
+        p.tune(feasm.TUNE_OWNER_FLAT, 10)
     p.free()
 
 
