@@ -74,12 +74,13 @@ def copy_factor(values, copy_mib):
     return copy_mib * (1 << 20) / best
 
 
-def summarize(trace, fetch, write, kernel, copy_mib, workload, command, algorithmic_bytes=None):
+def summarize(trace, fetch, write, kernel, copy_mib, workload, command, algorithmic_bytes=None,
+              title=None):
     durs = kernel_durations(trace)
     names = _match(durs, kernel)
     if not names:
         raise SystemExit(f"kernel {kernel!r} not in trace; have {sorted(durs)[:8]}")
-    lines = [f"# {kernel} on {workload}", ""]
+    lines = [f"# {title or kernel} on {workload}", ""]
     lines.append(f"source hash: {source_hash()}")
     lines.append("")
     lines.append("Commands (run from the repository root on the GPU host):")
@@ -93,6 +94,20 @@ def summarize(trace, fetch, write, kernel, copy_mib, workload, command, algorith
         v = durs[nme]
         lines.append(f"| {nme[:100]} | {len(v)} | {sum(v) / len(v):.2f} | {min(v):.2f} |")
     lines.append("")
+    copies = [d for k in _match(durs, r"copyBuffer|copy") for d in durs[k]]
+    if copies and copy_mib:
+        # the copy kernel of the same run reads and writes copy_mib MiB: a
+        # practical ceiling for streaming kernels on this device
+        big = max(copies)
+        best = min(d for d in copies if d > 0.5 * big)  # fastest of the large copies
+        lines.append(f"Device copy of {copy_mib} MiB in the same run: {best:.1f} us, "
+                     f"{2 * copy_mib * (1 << 20) / (best * 1e-6) / 1e9:.0f} GB/s read+write")
+        lines.append("")
+    if algorithmic_bytes:
+        mean = sum(durs[names[0]]) / len(durs[names[0]])
+        lines.append(f"algorithmic bytes / mean duration: "
+                     f"{algorithmic_bytes / (mean * 1e-6) / 1e9:.0f} GB/s")
+        lines.append("")
     fv = counter_values(fetch, "FETCH_SIZE") if fetch else {}
     wv = counter_values(write, "WRITE_SIZE") if write else {}
     ff = copy_factor(fv, copy_mib) if fv else None
@@ -140,10 +155,11 @@ def main():
     ap.add_argument("--workload", default="hex64")
     ap.add_argument("--command", action="append", default=[])
     ap.add_argument("--algorithmic-bytes", type=int)
+    ap.add_argument("--title")
     ap.add_argument("--out")
     a = ap.parse_args()
     text = summarize(a.trace, a.fetch, a.write, a.kernel, a.copy_mib, a.workload, a.command,
-                     a.algorithmic_bytes)
+                     a.algorithmic_bytes, a.title)
     if a.out:
         with open(a.out, "w") as f:
             f.write(text)
