@@ -15,6 +15,7 @@
  *   - CRAC linear block search ............................ Section 2.2, "Linear block search" listing
  *   - sequential assembly G(D(r),D(c)) += K(r,c) .......... Section 3.1, "Sequential assembly" listing
  *   - greedy first-fit element colouring .................. Section 3.3 (colouring listing and text)
+ *   - matrix-vector product y = G x, CSR and over CRAC runs  Conclusions and outlook
  *
  * Indices are 0-based and 64-bit.  Floating point is plain FP64 with
  * round-to-nearest adds in the stated order; build with -O2
@@ -492,4 +493,47 @@ int orc_rows(const int32_t* conn, int64_t E, int32_t k, int32_t d, int64_t n_nod
     free(ptr);
     free(el);
     return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Matrix-vector product y = G x, the use of the CRAC runs the paper names
+ * in its conclusions and outlook.  Definition: y[i] = sum over the stored
+ * entries (i, j) of row i of values * x[j], summed in increasing column
+ * order, each product and each sum rounded (no fused multiply-add).
+ * yabs (optional) receives sum |values * x[j]|, which bounds the rounding
+ * error of any other order.                                             */
+void orc_spmv_csr(const int64_t* row_ptr, const int64_t* col_idx, int64_t n_rows,
+                  const double* values, const double* x, double* y, double* yabs)
+{
+    for (int64_t i = 0; i < n_rows; ++i) {
+        double s = 0.0, a = 0.0;
+        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+            const double t = values[p] * x[col_idx[p]];
+            s = s + t;
+            a = a + fabs(t);
+        }
+        y[i] = s;
+        if (yabs)
+            yabs[i] = a;
+    }
+}
+
+/* The same product read through the CRAC arrays: row i holds the pairs
+ * ca[crac_row_ptr[i] .. crac_row_ptr[i+1]) (two integers per run: first
+ * column, position of its first value).  A run's values are consecutive
+ * and end where the next pair's values begin (the next run of the row, the
+ * next row's first run, or the final pair (n_cols, nnz)); value t of the
+ * run multiplies x[first column + t].                                   */
+void orc_spmv_crac(const int64_t* crac_row_ptr, const int64_t* ca, int64_t n_rows,
+                   const double* values, const double* x, double* y)
+{
+    for (int64_t i = 0; i < n_rows; ++i) {
+        double s = 0.0;
+        for (int64_t q = crac_row_ptr[i]; q < crac_row_ptr[i + 1]; q += 2) {
+            const int64_t col = ca[q], pos = ca[q + 1], end = ca[q + 3];
+            for (int64_t t = 0; t < end - pos; ++t)
+                s = s + values[pos + t] * x[col + t];
+        }
+        y[i] = s;
+    }
 }

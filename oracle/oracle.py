@@ -65,6 +65,8 @@ def lib():
         L.orc_colouring_valid.restype = ctypes.c_int
         L.orc_rows.argtypes = [P, I64, I32, I32, I64, P, I64, P, I64, P, P, P, P]
         L.orc_rows.restype = ctypes.c_int
+        L.orc_spmv_csr.argtypes = [P, P, I64, P, P, P, P]
+        L.orc_spmv_crac.argtypes = [P, P, I64, P, P, P]
         L.orc_free.argtypes = [P]
         _lib = L
     return _lib
@@ -206,3 +208,29 @@ def rows(conn, d, n_nodes, ke, req_rows, cap=4096):
         raise ValueError(f"orc_rows failed: {rc}")
     return [(cols[q, : ln[q]].copy(), vals[q, : ln[q]].copy(), absv[q, : ln[q]].copy())
             for q in range(req.size)]
+
+
+def spmv_csr(row_ptr, col_idx, values, x, with_abs=True):
+    """y = G x through CSR, summed in column order; returns (y, yabs or None)."""
+    row_ptr = _c(row_ptr, np.int64)
+    col_idx = _c(col_idx, np.int64)
+    values = _c(values, np.float64)
+    x = _c(x, np.float64)
+    n_rows = row_ptr.size - 1
+    y = np.empty(n_rows, dtype=np.float64)
+    ya = np.empty(n_rows, dtype=np.float64) if with_abs else None
+    lib().orc_spmv_csr(_p(row_ptr), _p(col_idx), n_rows, _p(values), _p(x), _p(y),
+                       _p(ya) if with_abs else None)
+    return y, ya
+
+
+def spmv_crac(crac_row_ptr, ca, values, x):
+    """y = G x through the CRAC runs, summed in column order."""
+    crac_row_ptr = _c(crac_row_ptr, np.int64)
+    ca = _c(ca, np.int64)
+    values = _c(values, np.float64)
+    x = _c(x, np.float64)
+    n_rows = crac_row_ptr.size - 1
+    y = np.empty(n_rows, dtype=np.float64)
+    lib().orc_spmv_crac(_p(crac_row_ptr), _p(ca), n_rows, _p(values), _p(x), _p(y))
+    return y
