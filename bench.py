@@ -235,6 +235,19 @@ def main():
             reasm[name]["algorithmic_bytes"] = nb
             reasm[name]["GBps"] = nb / (reasm[name]["mean"] * 1e-3) / 1e9
 
+    log("[bench] matrix-vector product y = G x")
+    xv = torch.randn(p.n_rows, dtype=torch.float64, device=dev)
+    yv = torch.empty_like(xv)
+    spmv = {}
+    # values, the format's index arrays and x read once, y written once
+    for name, fn, index_bytes in (("csr", feasm.spmv_csr, (p.n_rows + 1) * 4 + p.nnz * 4),
+                                  ("crac", feasm.spmv_crac, (p.n_rows + 1) * 4 + p.n_ca * 4)):
+        st = stats(time_calls(lambda f=fn: f(p, values, xv, yv), max(reps, 50), args.warmup))
+        nb = p.nnz * 8 + index_bytes + 2 * p.n_rows * 8
+        st["algorithmic_bytes"] = nb
+        st["GBps"] = nb / (st["mean"] * 1e-3) / 1e9
+        spmv[name] = st
+
     best = min(variants, key=lambda k: variants[k]["assemble_ms"]["mean"])
     step = full[best]
     log(f"[bench] timed steps: {best} x {args.steps}")
@@ -291,6 +304,7 @@ def main():
                      "bytes_per_launch": v["algorithmic_bytes"],
                      "kernel_ms": kernel_ms},
         "reassembly_ms": reasm,
+        "spmv_ms": spmv,
         "pattern_build_ms": {"runs": pb_ms},
         "variants": variants,
     }

@@ -143,11 +143,14 @@ int assemble_crac(const feasm_pattern* p, const double* ke, double* values, int 
  * pattern is kept).  `fmt` is FEASM_FMT_CSR or FEASM_FMT_CRAC.  Returns the
  * same values as assemble_<fmt> with the same arguments (bitwise for the
  * row-owned and coloured strategies; within FP64 reordering for the atomic
- * one).  With the atomic or coloured strategy the first call on a handle
- * records each element's lookup results on the device and synchronises
- * `stream` (hence the non-const handle); later calls, on any stream and
- * concurrently, read the record instead of searching.  The first call must
- * not race another call on the same handle.  Otherwise asynchronous.
+ * one).  The first call on a handle records the lookup results on the
+ * device and synchronises `stream` (hence the non-const handle): for the
+ * atomic and coloured strategies each element's (row node, run) offsets,
+ * for the row-owned strategy the column offset of every element node in
+ * every owned row (int32 [n_elem*k][k]); each record is made once, by the
+ * first call of its strategy family.  Later calls, on any stream and
+ * concurrently, read the record instead of searching.  A recording call
+ * must not race another call on the same handle.  Otherwise asynchronous.
  */
 int reassemble_values(feasm_pattern* p, int fmt, const double* ke, double* values, int scatter,
                       hipStream_t stream);
@@ -199,6 +202,10 @@ int pattern_colouring(const feasm_pattern* p, const int64_t** colour_ptr,
  *   FEASM_TUNE_OWNER_PREFETCH       flat batches, rows longer than one batch:
  *                                   1 = issue the next batch's loads before the
  *                                   current batch is added (more registers)
+ *   FEASM_TUNE_SPMV_CHUNK           spmv_csr / spmv_crac: values a wavefront
+ *                                   stages in LDS at a time, 256, 512, 1024 or
+ *                                   2048 (0: 1024 for CSR, 512 for CRAC); rows
+ *                                   per wavefront follow
  * Returns EINVAL for an unknown key or value.
  */
 enum {
@@ -208,9 +215,31 @@ enum {
     FEASM_TUNE_OWNER_BATCH = 4,
     FEASM_TUNE_STRATEGY = 5,
     FEASM_TUNE_OWNER_FLAT = 6,
-    FEASM_TUNE_OWNER_PREFETCH = 7
+    FEASM_TUNE_OWNER_PREFETCH = 7,
+    FEASM_TUNE_SPMV_CHUNK = 8
 };
 int pattern_tune(feasm_pattern* p, int key, int64_t value);
+
+/*
+ * spmv_csr / spmv_crac -- sparse matrix-vector product y = G x with an
+ * assembled matrix (the conclusions and outlook name the product as the use
+ * of the CRAC runs; the definition is the usual one, n_cols = n_rows).
+ *   values  dev double [nnz]: the assembled values (the same array for both
+ *           formats)
+ *   x       dev double [n_rows]
+ *   y       dev double [n_rows], overwritten; must not overlap x
+ * spmv_csr reads row_ptr and col_idx; spmv_crac reads crac_row_ptr and the
+ * CRAC pairs, each run covering consecutive columns from its first column.
+ * Each y[i] sums its row's products values[p] * x[col] in increasing column
+ * order with every product and sum rounded separately, so both give the
+ * same bits as a sequential loop over the row.  Asynchronous on `stream`.
+ * Returns EINVAL for a null handle or buffer, a format the handle lacks, or
+ * overlapping x and y.
+ */
+int spmv_csr(const feasm_pattern* p, const double* values, const double* x, double* y,
+             hipStream_t stream);
+int spmv_crac(const feasm_pattern* p, const double* values, const double* x, double* y,
+              hipStream_t stream);
 
 /* Releases the handle and its device arrays (synchronises the device). NULL is ignored. */
 void pattern_free(feasm_pattern* p);

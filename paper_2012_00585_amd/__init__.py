@@ -36,6 +36,7 @@ TUNE_OWNER_BATCH = 4
 TUNE_STRATEGY = 5
 TUNE_OWNER_FLAT = 6
 TUNE_OWNER_PREFETCH = 7
+TUNE_SPMV_CHUNK = 8
 
 _HIP_D2D = 3  # hipMemcpyDeviceToDevice
 
@@ -199,6 +200,39 @@ def reassemble_values(p: Pattern, fmt: int, ke: torch.Tensor, values: torch.Tens
     _lib.check(_lib.load().reassemble_values(p.handle, fmt, _ptr(ke), _ptr(values), scatter,
                                              _stream(stream)), "reassemble_values")
     return values
+
+
+def _spmv_args(p: Pattern, values, x, y):
+    _require(values, torch.float64, "values")
+    _require(x, torch.float64, "x")
+    if values.numel() < p.nnz:
+        raise ValueError(f"values must hold nnz = {p.nnz} entries, got {values.numel()}")
+    if x.numel() != p.n_rows:
+        raise ValueError(f"x must hold n_rows = {p.n_rows} entries, got {x.numel()}")
+    if y is None:
+        y = torch.empty(p.n_rows, dtype=torch.float64, device=x.device)
+    _require(y, torch.float64, "y")
+    if y.numel() != p.n_rows:
+        raise ValueError(f"y must hold n_rows = {p.n_rows} entries, got {y.numel()}")
+    return y
+
+
+def spmv_csr(p: Pattern, values: torch.Tensor, x: torch.Tensor, y: torch.Tensor | None = None,
+             stream=None) -> torch.Tensor:
+    """y := G x through CSR (asynchronous)."""
+    y = _spmv_args(p, values, x, y)
+    _lib.check(_lib.load().spmv_csr(p.handle, _ptr(values), _ptr(x), _ptr(y), _stream(stream)),
+               "spmv_csr")
+    return y
+
+
+def spmv_crac(p: Pattern, values: torch.Tensor, x: torch.Tensor, y: torch.Tensor | None = None,
+              stream=None) -> torch.Tensor:
+    """y := G x through the CRAC runs (asynchronous)."""
+    y = _spmv_args(p, values, x, y)
+    _lib.check(_lib.load().spmv_crac(p.handle, _ptr(values), _ptr(x), _ptr(y), _stream(stream)),
+               "spmv_crac")
+    return y
 
 
 RECIPE_LAPLACIAN = 0

@@ -48,6 +48,8 @@ SIGNATURES = {
     "assemble_csr": (INT, [P, P, P, INT, P]),
     "assemble_crac": (INT, [P, P, P, INT, P]),
     "reassemble_values": (INT, [P, INT, P, P, INT, P]),
+    "spmv_csr": (INT, [P, P, P, P, P]),
+    "spmv_crac": (INT, [P, P, P, P, P]),
     "pattern_info": (INT, [P, PI64, PI64, PI64, PI32]),
     "pattern_arrays": (INT, [P, PP, PP, PP, PP]),
     "pattern_colouring": (INT, [P, PP, PP, PP]),

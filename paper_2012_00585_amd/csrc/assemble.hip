@@ -413,9 +413,10 @@ extern "C" int reassemble_values(feasm_pattern* p, int fmt, const double* ke, do
         FEASM_FAIL(FEASM_EINVAL, "reassemble_values: handle was built without CSR");
     if (fmt == FEASM_FMT_CRAC && !(p->flags & FEASM_BUILD_CRAC))
         FEASM_FAIL(FEASM_EINVAL, "reassemble_values: handle was built without CRAC");
-    // The element-centric strategies record their (row node, run) offsets on
-    // the first call and read them afterwards instead of searching; the
-    // row-owned strategy searches rows staged in LDS and needs no record.
+    // Both strategy families record their lookups on the first call and read
+    // the record afterwards instead of searching: the element-centric ones
+    // each element's (row node, run) offsets, the row-owned one the column
+    // offset of every element node in every owned row.
     int strategy = scatter & ~FEASM_ACCUMULATE;
     if (strategy == FEASM_SCATTER_AUTO) {
         strategy = p->tune_strategy;
@@ -492,6 +493,12 @@ extern "C" int pattern_tune(feasm_pattern* p, int key, int64_t value) {
         if (value != 0 && value != 8 && value != 16)
             FEASM_FAIL(FEASM_EINVAL, "pattern_tune: owner batch must be 8 or 16");
         p->tune_owner_batch = (int32_t)value;
+        return FEASM_OK;
+    }
+    if (key == FEASM_TUNE_SPMV_CHUNK) {
+        if (value != 0 && value != 256 && value != 512 && value != 1024 && value != 2048)
+            FEASM_FAIL(FEASM_EINVAL, "pattern_tune: spmv chunk must be 256, 512, 1024 or 2048");
+        p->tune_spmv_chunk = (int32_t)value;
         return FEASM_OK;
     }
     if (key == FEASM_TUNE_OWNER_PREFETCH) {

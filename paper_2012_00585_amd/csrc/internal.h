@@ -95,6 +95,7 @@ struct feasm_pattern {
     int32_t tune_strategy = 0;             // what FEASM_SCATTER_AUTO resolves to (0: row-owned)
     int32_t tune_owner_flat = 0;           // flat batches: -1 off, 0 auto, else entries per batch
     int32_t tune_owner_prefetch = 0;       // flat batches: issue the next batch early
+    int32_t tune_spmv_chunk = 0;           // matrix-vector product: values per LDS chunk
 };
 
 namespace feasm {

@@ -80,6 +80,9 @@ def test_numeric_calls_reject_null_handle(lib):
     assert lib.pattern_arrays(None, None, None, None, None) == -1
     assert lib.pattern_colouring(None, None, None, None) == -1
     assert lib.pattern_tune(None, 1, 0) == -1
+    assert lib.spmv_csr(None, d, d, d, None) == -1
+    assert b"spmv_csr: null handle" in lib.last_error()
+    assert lib.spmv_crac(None, d, d, d, None) == -1
     lib.pattern_free(None)  # ignored
 
 
