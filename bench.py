@@ -132,7 +132,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="hex64",
-                    choices=["hex64", "quad64", "tet40", "batch512", "serve"])
+                    choices=["hex64", "quad64", "tet40", "batch512", "serve", "refine"])
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="mean arrivals per second")
     ap.add_argument("--serve-slots", type=int, default=16)
@@ -169,6 +169,8 @@ def main():
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "refine":
+        return bench_refine(args)
     w, wdesc = workload(args.workload)
     log(f"[bench] {wdesc}: generating element matrices")
     ke = w.ke()
@@ -405,6 +407,80 @@ def bench_batch(args):
     b.free()
     for p in pats:
         p.free()
+    print(json.dumps(line), flush=True)
+
+
+def bench_refine(args):
+    """p- and d-refinement on structured quad meshes (the paper's p- and
+    d-benchmarks, Section 4): Q_p quads p = 1..8 on 48 x 48 elements (d = 1,
+    and d = 4 for p <= 4), and Q1 quads with d = 1..8 and 20 DOFs per node on
+    192 x 192 elements.  For each: pattern build, CSR and CRAC assembly with
+    the row-owned and the atomic strategy, the CRAC storage factor
+    gamma = n_ca / nnz, and the matrix-vector product."""
+    import torch
+
+    import paper_2012_00585_amd as feasm
+    from fe_inputs import matrices, meshes
+
+    dev = torch.device("cuda:0")
+    cases = ([("p", 48, p, 1) for p in range(1, 9)] + [("p", 48, p, 4) for p in range(1, 5)] +
+             [("d", 192, 1, d) for d in (1, 2, 3, 4, 5, 6, 7, 8, 20)])
+    rows = []
+    O, A = feasm.SCATTER_OWNER, feasm.SCATTER_ATOMIC
+    reps = max(args.steps, 5)
+    for bench_kind, m, pdeg, d in cases:
+        conn, nn = meshes.qp_quad_mesh(m, pdeg)
+        E, k = conn.shape
+        n = k * d
+        t0 = time.perf_counter()
+        pat = feasm.pattern_build(torch.from_numpy(conn).to(dev), d, nn,
+                                  feasm.BUILD_CSR | feasm.BUILD_CRAC)
+        build_ms = (time.perf_counter() - t0) * 1e3
+        if n * n * 8 <= 64 * 1024:
+            ke = feasm.generate_ke(feasm.RECIPE_SPD, E, n, seed=pdeg * 100 + d)
+        else:
+            ke = torch.from_numpy(matrices.ke_spd(E, n, seed=pdeg * 100 + d)).to(dev)
+        vals = torch.empty(pat.nnz, dtype=torch.float64, device=dev)
+        r = {"benchmark": bench_kind, "elements_per_side": m, "p": pdeg, "d": d, "n_elem": E,
+             "n": n, "n_rows": pat.n_rows, "nnz": pat.nnz, "n_ca": pat.n_ca,
+             "gamma": pat.n_ca / pat.nnz, "pattern_build_ms": build_ms}
+        for name, fn, sc in (("csr_owner", feasm.assemble_csr, O),
+                             ("crac_owner", feasm.assemble_crac, O),
+                             ("csr_atomic", feasm.assemble_csr, A),
+                             ("crac_atomic", feasm.assemble_crac, A)):
+            r[name + "_ms"] = stats(time_calls(lambda f=fn, c=sc: f(pat, ke, vals, c), reps,
+                                               args.warmup))["mean"]
+        # row-owned bytes: Ke, values written once, incidence, row index data
+        own_bytes = E * n * n * 8 + pat.nnz * 8 + 2 * E * k * 4
+        r["owner_GBps"] = own_bytes / (min(r["csr_owner_ms"], r["crac_owner_ms"]) * 1e-3) / 1e9
+        r["elements_per_s"] = E / (min(r["csr_owner_ms"], r["crac_owner_ms"]) * 1e-3)
+        x = torch.randn(pat.n_rows, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        r["spmv_csr_ms"] = stats(time_calls(lambda: feasm.spmv_csr(pat, vals, x, y), reps,
+                                            args.warmup))["mean"]
+        r["spmv_crac_ms"] = stats(time_calls(lambda: feasm.spmv_crac(pat, vals, x, y), reps,
+                                             args.warmup))["mean"]
+        log(f"[bench] {bench_kind}-benchmark m={m} p={pdeg} d={d}: nnz {pat.nnz} "
+            f"gamma {r['gamma']:.3f} owner csr {r['csr_owner_ms']:.3f} crac "
+            f"{r['crac_owner_ms']:.3f} ms, atomic csr {r['csr_atomic_ms']:.3f} crac "
+            f"{r['crac_atomic_ms']:.3f} ms, spmv csr {r['spmv_csr_ms']:.3f} crac "
+            f"{r['spmv_crac_ms']:.3f} ms")
+        rows.append(r)
+        pat.free()
+        del ke, vals, x, y
+    total_e = sum(r["n_elem"] for r in rows)
+    total_ms = sum(min(r["csr_owner_ms"], r["crac_owner_ms"]) for r in rows)
+    line = {
+        "metric": "element matrices assembled/s (p- and d-refinement sweep)",
+        "value": total_e / (total_ms * 1e-3), "unit": "element matrices/s", "n_gpus": 1,
+        "steps": reps, "warmup": args.warmup, "ms_per_step": total_ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "p-benchmark: Q_p quads p=1..8 on 48x48 (d=1; d=4 for p<=4); "
+                               "d-benchmark: Q1 quads on 192x192, d=1..8 and 20; SPD FP64 Ke",
+                   "step": "one row-owned assembly of every case, faster format each"},
+        "cases": rows,
+    }
     print(json.dumps(line), flush=True)
 
 

@@ -98,7 +98,7 @@ OwnShape owner_shape(const feasm_pattern* p, int fmt) {
     for (;; g <<= 1) {
         if (g > 64) return {0, 0, 0, 0};
         const int j = (int)ceil_div(dn, g);
-        const int jj = j <= 1 ? 1 : j <= 2 ? 2 : j <= 4 ? 4 : j <= 8 ? 8 : 16;
+        const int jj = j <= 1 ? 1 : j <= 2 ? 2 : j <= 4 ? 4 : j <= 8 ? 8 : j <= 16 ? 16 : 32;
         const int b = jj <= 2 ? 8 : jj == 4 ? 4 : jj == 8 ? 2 : 1;
         const int64_t idx = fmt == kMap ? 0
                             : fmt == kCSR ? (int64_t)p->d * p->max_deg : 2 * (int64_t)p->max_deg + 2;
@@ -193,12 +193,13 @@ int launch_owner_f(const feasm_pattern* p, OwnArgs& A, hipStream_t s) {
         case 6402: return launch_owner_t<FMT, 64, 2, 8>(p, A, s);
         case 6404: return launch_owner_t<FMT, 64, 4, 4>(p, A, s);
         case 6408: return launch_owner_t<FMT, 64, 8, 2>(p, A, s);
-        default: return launch_owner_t<FMT, 64, 16, 1>(p, A, s);
+        case 6416: return launch_owner_t<FMT, 64, 16, 1>(p, A, s);
+        default: return launch_owner_t<FMT, 64, 32, 1>(p, A, s);
     }
 }
 
 bool owner_fits(const feasm_pattern* p, int fmt) {
-    return (int64_t)p->d * p->n <= 1024 && owner_shape(p, fmt).g != 0;
+    return (int64_t)p->d * p->n <= 2048 && owner_shape(p, fmt).g != 0;
 }
 
 // Records every row-owned lookup (owner_map_node) for one node per block.
@@ -210,8 +211,8 @@ __global__ void __launch_bounds__(64) k_owner_map(OwnArgs A, int32_t* out) {
 
 int launch_owner(const feasm_pattern* p, int fmt, const double* ke, double* values, bool accumulate,
                  hipStream_t s, const int32_t* map = nullptr) {
-    if ((int64_t)p->d * p->n > 1024)
-        FEASM_FAIL(FEASM_ELIMIT, "row-owned assembly supports d * n <= 1024");
+    if ((int64_t)p->d * p->n > 2048)
+        FEASM_FAIL(FEASM_ELIMIT, "row-owned assembly supports d * n <= 2048");
     OwnArgs A{};
     A.conn = p->conn;
     A.k = p->k;

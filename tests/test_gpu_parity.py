@@ -131,6 +131,11 @@ CASES = [
     ("fan400_bignode", lambda: _fan(400), 1),
     ("repeated_node", _repeated, 2),
     ("unused_nodes", lambda: (meshes.quad_mesh(4)[0], 40), 1),
+    # p- and d-refinement shapes: Q6 quads with 3 DOFs (d*n = 441), Q1 quads
+    # with 8 and 20 DOFs per node (d*n = 256 and 1600)
+    ("q6quad2_d3", lambda: meshes.qp_quad_mesh(2, 6), 3),
+    ("quad4_d8", lambda: meshes.quad_mesh(4), 8),
+    ("quad3_d20", lambda: meshes.quad_mesh(3), 20),
 ]
 
 
