@@ -204,8 +204,9 @@ int pattern_colouring(const feasm_pattern* p, const int64_t** colour_ptr,
  *                                   current batch is added (more registers)
  *   FEASM_TUNE_SPMV_CHUNK           spmv_csr / spmv_crac: values a wavefront
  *                                   stages in LDS at a time, 256, 512, 1024 or
- *                                   2048 (0: 1024 for CSR, 512 for CRAC); rows
- *                                   per wavefront follow
+ *                                   2048 (0: 1024, or 512 for CRAC with at most
+ *                                   96 values per row on average); rows per
+ *                                   wavefront follow
  * Returns EINVAL for an unknown key or value.
  */
 enum {

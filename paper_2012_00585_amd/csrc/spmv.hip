@@ -5,8 +5,8 @@
 // One 64-lane wavefront takes R consecutive rows, whose values are one
 // contiguous range.  The range is processed in chunks of kChunk values:
 // column indices come from col_idx (CSR) or are expanded from the CRAC
-// pairs into LDS (each lane writes the columns of one run: first column +
-// offset), every lane forms products values[i] * x[col] for its values
+// pairs into LDS (value-parallel, whatever the run lengths), every lane
+// forms products values[i] * x[col] for its values
 // (coalesced loads of values and col_idx, gathers of x, all issued before
 // any is used) into an LDS buffer,
 // and lane r then adds row r's products in increasing column order.  Every
@@ -34,8 +34,14 @@ struct SpmvArgs {
 
 template <int FMT, int kChunk>
 __global__ void __launch_bounds__(64) k_spmv(SpmvArgs A) {
-    __shared__ double prod[kChunk];
-    __shared__ int32_t colb[FMT == 1 ? kChunk : 1];
+    // slot j of a chunk: first the CRAC column of position j, then (written
+    // by the lane that read the column) its product
+    union Slot {
+        double prod;
+        int32_t col;
+    };
+    __shared__ Slot slot[kChunk];
+    auto colb = [&](int32_t j) -> int32_t& { return slot[j].col; };
     const int l = threadIdx.x;
     const int64_t r0 = xcd_block(blockIdx.x, gridDim.x) * A.rows_per_wave;
     const int nr = (int)(A.n_rows - r0 < A.rows_per_wave ? A.n_rows - r0 : A.rows_per_wave);
@@ -60,9 +66,11 @@ __global__ void __launch_bounds__(64) k_spmv(SpmvArgs A) {
     double s = 0.0;
     for (int32_t c0 = vs; c0 < ve; c0 += kChunk) {
         const int32_t c1 = std::min(c0 + kChunk, ve);
-        if (FMT == 1) {
-            // PU pairs per lane per group, their loads issued together; a run
-            // ends where the next pair's values begin
+        // CRAC: expand the runs of the chunk into column indices.  Short runs
+        // (the wavefront's values per pair at most 16) are written by one
+        // lane per pair, longer ones by all lanes, one run at a time.
+        const bool short_runs = FMT == 1 && (int64_t)(ve - vs) * 2 <= (int64_t)16 * (pe - pb);
+        if (FMT == 1 && short_runs) {
             constexpr int PU = kChunk >= 512 ? kChunk / 256 : 1;
             for (int32_t g = pb; g < pe; g += 128 * PU) {
                 int32_t first[PU], ps[PU], pn[PU];
@@ -73,13 +81,35 @@ __global__ void __launch_bounds__(64) k_spmv(SpmvArgs A) {
                     if (q < pe) {
                         first[u] = A.ca[q];
                         ps[u] = A.ca[q + 1];
-                        pn[u] = A.ca[q + 3];
+                        pn[u] = A.ca[q + 3];  // a run ends where the next pair's values begin
                     }
                 }
 #pragma unroll
                 for (int u = 0; u < PU; ++u) {
                     const int32_t a = std::max(ps[u], c0), b = std::min(pn[u], c1);
-                    for (int32_t i = a; i < b; ++i) colb[i - c0] = first[u] + (i - ps[u]);
+                    for (int32_t i = a; i < b; ++i) colb(i - c0) = first[u] + (i - ps[u]);
+                }
+            }
+            __syncthreads();
+        } else if (FMT == 1) {
+            // Long runs: the lanes fill one run at a time, 64 positions per
+            // instruction; each group of 64 pairs is loaded one per lane and
+            // read back with readlane.
+            for (int32_t g = pb; g < pe; g += 128) {
+                const int32_t q = g + 2 * l;
+                int32_t first = 0, ps = 0, pn = 0;
+                if (q < pe) {
+                    first = A.ca[q];
+                    ps = A.ca[q + 1];
+                    pn = A.ca[q + 3];  // a run ends where the next pair's values begin
+                }
+                const int cnt = std::min(64, (pe - g) >> 1);
+                for (int k = 0; k < cnt; ++k) {
+                    const int32_t ks = __builtin_amdgcn_readlane(ps, k);
+                    const int32_t ke = __builtin_amdgcn_readlane(pn, k);
+                    const int32_t kd = __builtin_amdgcn_readlane(first, k) - ks;
+                    const int32_t lo = std::max(ks, c0), hi = std::min(ke, c1);
+                    for (int32_t i = lo + l; i < hi; i += 64) colb(i - c0) = i + kd;
                 }
             }
             __syncthreads();
@@ -95,7 +125,7 @@ __global__ void __launch_bounds__(64) k_spmv(SpmvArgs A) {
             cu[u] = 0;
             vu[u] = 0.0;
             if (i < c1) {
-                cu[u] = FMT == 0 ? __builtin_nontemporal_load(A.col_idx + i) : colb[i - c0];
+                cu[u] = FMT == 0 ? __builtin_nontemporal_load(A.col_idx + i) : colb(i - c0);
                 vu[u] = __builtin_nontemporal_load(A.values + i);
             }
         }
@@ -103,12 +133,12 @@ __global__ void __launch_bounds__(64) k_spmv(SpmvArgs A) {
         for (int u = 0; u < U; ++u) xu[u] = c0 + l + 64 * u < c1 ? A.x[cu[u]] : 0.0;
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (c0 + l + 64 * u < c1) prod[l + 64 * u] = vu[u] * xu[u];
+            if (c0 + l + 64 * u < c1) slot[l + 64 * u].prod = vu[u] * xu[u];
         __syncthreads();
         if (l < nr) {
             const int32_t a = std::max(rb, c0), b = std::min(re, c1);
 #pragma unroll 8
-            for (int32_t i = a; i < b; ++i) s = s + prod[i - c0];
+            for (int32_t i = a; i < b; ++i) s = s + slot[i - c0].prod;
         }
         __syncthreads();
     }
@@ -137,8 +167,10 @@ int spmv_impl(const feasm_pattern* p, int fmt, const double* values, const doubl
     A.y = y;
     A.n_rows = p->n_rows;
     // values per LDS chunk, and as many rows per wavefront as fill one
-    const int chunk = p->tune_spmv_chunk > 0 ? p->tune_spmv_chunk : fmt == 0 ? 1024 : 512;
     const int64_t avg = std::max<int64_t>(1, p->nnz / p->n_rows);
+    const int chunk = p->tune_spmv_chunk > 0 ? p->tune_spmv_chunk
+                      : fmt == 0 || avg > 96  ? 1024
+                                              : 512;
     A.rows_per_wave = (int32_t)std::min<int64_t>(63, std::max<int64_t>(1, chunk / avg));
     const unsigned blocks = (unsigned)ceil_div(p->n_rows, A.rows_per_wave);
 #define FEASM_SPMV(CH)                                          \
