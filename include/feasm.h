@@ -192,13 +192,16 @@ int pattern_colouring(const feasm_pattern* p, const int64_t** colour_ptr,
  *   FEASM_TUNE_STRATEGY             the strategy FEASM_SCATTER_AUTO resolves to
  *                                   for this handle (and in batches)
  *   FEASM_TUNE_OWNER_FLAT           row-owned strategy: one node row per
- *                                   wavefront, the element rows of a batch of 8
- *                                   or 16 entries read as one flat array; 0 =
- *                                   auto (8 if no node has more than 8 incident
- *                                   entries, else 16), -1 = off.  Compiled for
- *                                   8-node hexes and 10-node tets with 3 DOFs
- *                                   per node; other shapes keep the launch the
- *                                   settings above choose
+ *                                   wavefront, the element rows of a batch of 4,
+ *                                   8 or 16 entries read as one flat array; 0 =
+ *                                   auto (4 for d*n > 192, else 8 if no node has
+ *                                   more than 8 incident entries, else 16), -1 =
+ *                                   off.  Compiled for 8-node hexes and 10-node
+ *                                   tets with 3 DOFs per node, and, for rows of
+ *                                   at most 4 or 8 entries, for Q3/Q4 quads with
+ *                                   4 DOFs and Q1 quads with 4 to 8; other
+ *                                   shapes keep the launch the settings above
+ *                                   choose
  *   FEASM_TUNE_OWNER_PREFETCH       flat batches, rows longer than one batch:
  *                                   1 = issue the next batch's loads before the
  *                                   current batch is added (more registers)

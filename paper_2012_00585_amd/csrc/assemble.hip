@@ -139,12 +139,20 @@ int launch_owner_f(const feasm_pattern* p, OwnArgs& A, hipStream_t s) {
     A.idx_ints = FMT == kMap ? 0 : FMT == kCSR ? p->d * p->max_deg : 2 * p->max_deg + 2;
     A.acc_doubles = p->d * p->d * p->max_deg;
     A.group_bytes = sh.group_bytes;
-    // Flat, pipelined batches (tuned): one node row per wavefront, B entries
-    // per batch, for the element shapes they are compiled for.
-    // By default (setting 0) they are used wherever they are compiled, with
-    // 8 entries per batch where no row is longer, else 16.
+    // Flat, pipelined batches: one node row per wavefront, B entries per
+    // batch, for the element shapes they are compiled for: 8-node hexes and
+    // 10-node tets with 3 DOFs per node (every mode), and, for rows of at most
+    // B entries, Q3/Q4 quads with 4 DOFs and Q1 quads with 4 to 8.  (High-order
+    // quads with 1 DOF, whose rows mostly have one entry, are faster with
+    // several rows per wavefront.)  By default (setting 0) they are used wherever they are
+    // compiled, with B = 4 for rows of more than 192 values, else 8 where no
+    // node has more incident entries, else 16.
     if (p->tune_owner_flat >= 0 && sh.g == 64) {
-        const int B = p->tune_owner_flat > 0 ? p->tune_owner_flat : p->max_inc <= 8 ? 8 : 16;
+        const int dn = p->d * p->n;
+        const int B = p->tune_owner_flat > 0 ? p->tune_owner_flat
+                      : dn > 192             ? 4
+                      : p->max_inc <= 8      ? 8
+                                             : 16;
         const size_t lds = (size_t)A.group_bytes + (size_t)2 * B * p->k * 4;
         if (lds <= 64 * 1024) {
             const unsigned blocks = (unsigned)p->n_nodes;
@@ -159,7 +167,19 @@ int launch_owner_f(const feasm_pattern* p, OwnArgs& A, hipStream_t s) {
         FEASM_HIP(hipGetLastError());                                                   \
         return FEASM_OK;                                                                \
     }
+#define FEASM_PIPE_ONE(DD, NN, BB)                                                      \
+    if (p->d == DD && p->n == NN && B == BB && p->max_inc <= BB) {                     \
+        k_owner_pipe<FMT, DD, NN, BB, 0><<<blocks, 64, lds, s>>>(A);                   \
+        FEASM_HIP(hipGetLastError());                                                   \
+        return FEASM_OK;                                                                \
+    }
+#define FEASM_PIPE_SHAPE(DD, NN) FEASM_PIPE_ONE(DD, NN, 4) FEASM_PIPE_ONE(DD, NN, 8)
             FEASM_PIPE(3, 24, 8) FEASM_PIPE(3, 24, 16) FEASM_PIPE(3, 30, 8) FEASM_PIPE(3, 30, 16)
+            FEASM_PIPE_SHAPE(4, 64) FEASM_PIPE_SHAPE(4, 100) FEASM_PIPE_SHAPE(4, 16)
+            FEASM_PIPE_SHAPE(5, 20)
+            FEASM_PIPE_SHAPE(6, 24) FEASM_PIPE_SHAPE(7, 28) FEASM_PIPE_SHAPE(8, 32)
+#undef FEASM_PIPE_SHAPE
+#undef FEASM_PIPE_ONE
 #undef FEASM_PIPE
         }
     }
@@ -509,8 +529,9 @@ extern "C" int pattern_tune(feasm_pattern* p, int key, int64_t value) {
         return FEASM_OK;
     }
     if (key == FEASM_TUNE_OWNER_FLAT) {
-        if (value != -1 && value != 0 && value != 8 && value != 16)
-            FEASM_FAIL(FEASM_EINVAL, "pattern_tune: flat batch must be -1 (off), 0 (auto), 8 or 16");
+        if (value != -1 && value != 0 && value != 4 && value != 8 && value != 16)
+            FEASM_FAIL(FEASM_EINVAL,
+                       "pattern_tune: flat batch must be -1 (off), 0 (auto), 4, 8 or 16");
         p->tune_owner_flat = (int32_t)value;
         return FEASM_OK;
     }
