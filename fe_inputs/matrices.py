@@ -93,3 +93,15 @@ def values_on_pattern(rows, cols, seed: int = 0):
         z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
         z = z ^ (z >> np.uint64(31))
     return (z >> np.uint64(11)).astype(np.float64) * 2.0 ** -52 - 1.0
+
+
+def hex_materials(E: int, d: int, seed: int = 0):
+    """Per-element material parameters: ``[E]`` conductivities in [0.5, 2)
+    for d = 1, ``[E, 2]`` Lame parameters (lambda in [0.5, 2), mu in
+    [0.25, 1)) for d = 3."""
+    rng = np.random.default_rng(seed)
+    if d == 1:
+        return 0.5 + 1.5 * rng.random(E)
+    lam = 0.5 + 1.5 * rng.random(E)
+    mu = 0.25 + 0.75 * rng.random(E)
+    return np.stack([lam, mu], axis=1)

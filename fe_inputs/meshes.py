@@ -125,3 +125,21 @@ def permute_nodes(conn, n_nodes: int, seed: int):
     """Relabel node ids with ``default_rng(seed).permutation(n_nodes)``."""
     perm = np.random.default_rng(seed).permutation(n_nodes)
     return perm[np.asarray(conn, dtype=np.int64)].astype(np.int32)
+
+
+def hex_coords(m: int, my: int | None = None, mz: int | None = None, jitter: float = 0.0,
+               seed: int = 0, size: float = 1.0):
+    """Node coordinates ``[n_nodes, 3]`` for :func:`hex_mesh`'s numbering.
+
+    Node ``(i, j, k)`` sits at ``h (i, j, k)`` with ``h = size / m``, moved by
+    ``jitter * h`` times a seeded uniform offset in ``[-1/2, 1/2)^3`` (elements
+    stay valid for ``jitter`` below about 0.3)."""
+    my = m if my is None else my
+    mz = m if mz is None else mz
+    h = size / m
+    k, j, i = np.meshgrid(np.arange(mz + 1), np.arange(my + 1), np.arange(m + 1), indexing="ij")
+    x = np.stack([i.ravel(), j.ravel(), k.ravel()], axis=1).astype(np.float64) * h
+    if jitter:
+        rng = np.random.default_rng(seed)
+        x = x + jitter * h * (rng.random(x.shape) - 0.5)
+    return x

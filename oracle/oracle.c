@@ -16,6 +16,8 @@
  *   - sequential assembly G(D(r),D(c)) += K(r,c) .......... Section 3.1, "Sequential assembly" listing
  *   - greedy first-fit element colouring .................. Section 3.3 (colouring listing and text)
  *   - matrix-vector product y = G x, CSR and over CRAC runs  Conclusions and outlook
+ *   - 8-node hexahedron stiffness (Laplace, elasticity) .... Remark 1 (the element
+ *     matrix the paper replaces by a dummy); textbook trilinear element
  *
  * Indices are 0-based and 64-bit.  Floating point is plain FP64 with
  * round-to-nearest adds in the stated order; build with -O2
@@ -536,4 +538,113 @@ void orc_spmv_crac(const int64_t* crac_row_ptr, const int64_t* ca, int64_t n_row
         }
         y[i] = s;
     }
+}
+
+/* ------------------------------------------------------------------ */
+/* Element stiffness of the 8-node trilinear hexahedron -- the computation
+ * the paper replaces by a dummy matrix (Remark 1); textbook isoparametric
+ * element.  Local nodes: the bottom face (zeta = -1) counter-clockwise from
+ * (-1,-1), then the top face (zeta = +1) in the same order.  Shape function
+ * N_a = (1 + xi_a xi)(1 + eta_a eta)(1 + zeta_a zeta) / 8.  Quadrature: the
+ * 2x2x2 Gauss rule, points +-1/sqrt(3), weights 1, in the order xi fastest,
+ * then eta, then zeta.  With J_ij = dx_i/dxi_j and g_a = J^-T grad_xi N_a:
+ *   d = 1 (Laplace, mat[0] = kappa):
+ *       K_ab = sum_q kappa (g_a . g_b) det J
+ *   d = 3 (isotropic elasticity, mat[0] = lambda, mat[1] = mu), local DOF
+ *       3a + i:
+ *       K_(a,i)(b,j) = sum_q [lambda g_a,i g_b,j + mu (g_a,j g_b,i +
+ *                       delta_ij g_a . g_b)] det J
+ * x holds the 8 nodes' coordinates (x[3a + i]); K is n x n row-major with
+ * n = 8 d; kabs (optional) receives sum_q |each term| per entry, a bound
+ * for the rounding error of any other evaluation order.  Returns ORC_OK,
+ * or ORC_ERANGE if det J <= 0 at a quadrature point.                    */
+static const int HEX8_REF[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
+                                   {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
+
+int orc_hex8_stiffness(const double* x, int32_t d, const double* mat, double* K, double* kabs)
+{
+    const int32_t n = 8 * d;
+    for (int32_t i = 0; i < n * n; ++i) {
+        K[i] = 0.0;
+        if (kabs)
+            kabs[i] = 0.0;
+    }
+    const double gp = 1.0 / sqrt(3.0);
+    for (int q = 0; q < 8; ++q) {
+        const double xi[3] = {(q & 1) ? gp : -gp, (q & 2) ? gp : -gp, (q & 4) ? gp : -gp};
+        double dN[8][3]; /* d N_a / d xi_j */
+        for (int a = 0; a < 8; ++a) {
+            double f[3];
+            for (int j = 0; j < 3; ++j)
+                f[j] = 1.0 + HEX8_REF[a][j] * xi[j];
+            dN[a][0] = HEX8_REF[a][0] * f[1] * f[2] / 8.0;
+            dN[a][1] = f[0] * HEX8_REF[a][1] * f[2] / 8.0;
+            dN[a][2] = f[0] * f[1] * HEX8_REF[a][2] / 8.0;
+        }
+        double J[3][3] = {{0}};
+        for (int a = 0; a < 8; ++a)
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j)
+                    J[i][j] += x[3 * a + i] * dN[a][j];
+        /* inverse by cofactors: Jinv = adj(J) / det J */
+        double C[3][3];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+                C[i][j] = J[i1][j1] * J[i2][j2] - J[i1][j2] * J[i2][j1]; /* cofactor of J_ij */
+            }
+        const double det = J[0][0] * C[0][0] + J[0][1] * C[0][1] + J[0][2] * C[0][2];
+        if (!(det > 0.0))
+            return ORC_ERANGE;
+        /* g_a,i = sum_j (J^-1)_ji dN_a,j and (J^-1)_ji = C_ij / det */
+        double g[8][3];
+        for (int a = 0; a < 8; ++a)
+            for (int i = 0; i < 3; ++i) {
+                double s = 0.0;
+                for (int j = 0; j < 3; ++j)
+                    s += C[i][j] / det * dN[a][j];
+                g[a][i] = s;
+            }
+        for (int a = 0; a < 8; ++a)
+            for (int b = 0; b < 8; ++b) {
+                const double dot = g[a][0] * g[b][0] + g[a][1] * g[b][1] + g[a][2] * g[b][2];
+                if (d == 1) {
+                    const double t = mat[0] * dot * det;
+                    K[a * n + b] += t;
+                    if (kabs)
+                        kabs[a * n + b] += fabs(t);
+                    continue;
+                }
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j) {
+                        const double t1 = mat[0] * g[a][i] * g[b][j] * det;
+                        const double t2 = mat[1] * g[a][j] * g[b][i] * det;
+                        const double t3 = i == j ? mat[1] * dot * det : 0.0;
+                        const int64_t p = (int64_t)(3 * a + i) * n + 3 * b + j;
+                        K[p] += t1 + t2 + t3;
+                        if (kabs)
+                            kabs[p] += fabs(t1) + fabs(t2) + fabs(t3);
+                    }
+            }
+    }
+    return ORC_OK;
+}
+
+/* Element matrices of a whole hexahedral mesh: K[e] from the coordinates of
+ * conn[e] and mat[e * (d == 1 ? 1 : 2)].                                 */
+int orc_hex8_matrices(const int32_t* conn, int64_t E, const double* coords, int32_t d,
+                      const double* mat, double* K, double* kabs)
+{
+    const int32_t n = 8 * d, m = d == 1 ? 1 : 2;
+    for (int64_t e = 0; e < E; ++e) {
+        double x[24];
+        for (int a = 0; a < 8; ++a)
+            for (int i = 0; i < 3; ++i)
+                x[3 * a + i] = coords[3 * (int64_t)conn[8 * e + a] + i];
+        const int rc = orc_hex8_stiffness(x, d, mat + m * e, K + e * (int64_t)n * n,
+                                          kabs ? kabs + e * (int64_t)n * n : NULL);
+        if (rc != ORC_OK)
+            return rc;
+    }
+    return ORC_OK;
 }

@@ -67,6 +67,10 @@ def lib():
         L.orc_rows.restype = ctypes.c_int
         L.orc_spmv_csr.argtypes = [P, P, I64, P, P, P, P]
         L.orc_spmv_crac.argtypes = [P, P, I64, P, P, P]
+        L.orc_hex8_stiffness.argtypes = [P, I32, P, P, P]
+        L.orc_hex8_stiffness.restype = ctypes.c_int
+        L.orc_hex8_matrices.argtypes = [P, I64, P, I32, P, P, P]
+        L.orc_hex8_matrices.restype = ctypes.c_int
         L.orc_free.argtypes = [P]
         _lib = L
     return _lib
@@ -234,3 +238,33 @@ def spmv_crac(crac_row_ptr, ca, values, x):
     y = np.empty(n_rows, dtype=np.float64)
     lib().orc_spmv_crac(_p(crac_row_ptr), _p(ca), n_rows, _p(values), _p(x), _p(y))
     return y
+
+
+def hex8_stiffness(x, d, mat):
+    """Stiffness of one 8-node hexahedron: x [8, 3], d 1 or 3, mat (kappa,)
+    or (lambda, mu).  Returns (K [8d, 8d], kabs)."""
+    x = _c(x, np.float64)
+    mat = _c(mat, np.float64)
+    n = 8 * d
+    K = np.empty((n, n))
+    A = np.empty((n, n))
+    rc = lib().orc_hex8_stiffness(_p(x), d, _p(mat), _p(K), _p(A))
+    if rc != 0:
+        raise ValueError(f"orc_hex8_stiffness failed: {rc}")
+    return K, A
+
+
+def hex8_matrices(conn, coords, d, mat, with_abs=True):
+    """Element matrices [E, 8d, 8d] of a hexahedral mesh (and their term bounds)."""
+    conn = _c(conn, np.int32)
+    coords = _c(coords, np.float64)
+    mat = _c(mat, np.float64)
+    E = conn.shape[0]
+    n = 8 * d
+    K = np.empty((E, n, n))
+    A = np.empty((E, n, n)) if with_abs else None
+    rc = lib().orc_hex8_matrices(_p(conn), E, _p(coords), d, _p(mat), _p(K),
+                                 _p(A) if with_abs else None)
+    if rc != 0:
+        raise ValueError(f"orc_hex8_matrices failed: {rc}")
+    return K, A
