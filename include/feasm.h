@@ -245,6 +245,39 @@ int spmv_csr(const feasm_pattern* p, const double* values, const double* x, doub
 int spmv_crac(const feasm_pattern* p, const double* values, const double* x, double* y,
               hipStream_t stream);
 
+/*
+ * Element stiffness of 8-node trilinear hexahedra (the computation the paper
+ * replaces by a dummy matrix, Remark 1; textbook isoparametric element).
+ * The handle's elements must have k = 8 nodes, in the order: bottom face
+ * (zeta = -1) counter-clockwise from (-1,-1), then the top face in the same
+ * order; d = 1 gives the scalar Laplace matrix K_ab = sum_q kappa (g_a . g_b)
+ * det J, d = 3 isotropic linear elasticity K_(a,i)(b,j) = sum_q [lambda
+ * g_a,i g_b,j + mu (g_a,j g_b,i + delta_ij g_a . g_b)] det J (local DOF
+ * 3a + i), with the 2x2x2 Gauss rule (points +-1/sqrt(3), xi fastest), J_ij
+ * = dx_i/dxi_j and g_a,i = sum_j C_ij / det J * dN_a/dxi_j (C: cofactors of
+ * J).  Each entry is that sequence of correctly rounded operations in that
+ * order (no fused multiply-add).
+ *   coords    dev double [n_nodes][3]
+ *   material  dev double [n_elem] (kappa) for d = 1, [n_elem][2] (lambda,
+ *             mu) for d = 3
+ * hex8_element_matrices writes ke (dev double [n_elem][8d][8d]), for the
+ * two-pass path (then assemble_csr / assemble_crac).
+ * assemble_hex8 fuses the two: values (dev double [nnz]) := G, or += G with
+ * flags = FEASM_ACCUMULATE, computing each node's row block of every
+ * incident element inside the row-owned assembly (no element matrices in
+ * memory); fmt is FEASM_FMT_CSR or FEASM_FMT_CRAC.  Values are summed in
+ * element order, as the sequential listing, so they equal a sequential
+ * assembly of hex8_element_matrices' output bit for bit.
+ * Asynchronous on `stream`; elements must not be inverted (det J > 0; not
+ * checked).  Returns EINVAL for a null handle or buffer, k != 8, d not 1 or
+ * 3, a format the handle lacks or an unknown flag; ELIMIT (assemble_hex8)
+ * if a node row does not fit the LDS accumulator.
+ */
+int hex8_element_matrices(const feasm_pattern* p, const double* coords, const double* material,
+                          double* ke, hipStream_t stream);
+int assemble_hex8(const feasm_pattern* p, int fmt, const double* coords, const double* material,
+                  double* values, int flags, hipStream_t stream);
+
 /* Releases the handle and its device arrays (synchronises the device). NULL is ignored. */
 void pattern_free(feasm_pattern* p);
 

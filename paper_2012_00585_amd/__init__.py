@@ -235,6 +235,48 @@ def spmv_crac(p: Pattern, values: torch.Tensor, x: torch.Tensor, y: torch.Tensor
     return y
 
 
+def _hex8_args(p: Pattern, coords, material):
+    _require(coords, torch.float64, "coords")
+    _require(material, torch.float64, "material")
+    if coords.numel() != 3 * p.n_nodes:
+        raise ValueError(f"coords must hold 3 * n_nodes = {3 * p.n_nodes} values")
+    m = 1 if p.dofs_per_node == 1 else 2
+    if material.numel() != m * p.n_elem:
+        raise ValueError(f"material must hold {m} * n_elem = {m * p.n_elem} values")
+
+
+def hex8_element_matrices(p: Pattern, coords: torch.Tensor, material: torch.Tensor,
+                          ke: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Element stiffness matrices of 8-node hexahedra (Laplace for d = 1,
+    elasticity for d = 3) into ke [n_elem, 8d, 8d] (asynchronous)."""
+    _hex8_args(p, coords, material)
+    if ke is None:
+        ke = torch.empty((p.n_elem, p.n, p.n), dtype=torch.float64, device=coords.device)
+    _require(ke, torch.float64, "ke")
+    if ke.numel() < p.n_elem * p.n * p.n:
+        raise ValueError("ke too small")
+    _lib.check(_lib.load().hex8_element_matrices(p.handle, _ptr(coords), _ptr(material), _ptr(ke),
+                                                 _stream(stream)), "hex8_element_matrices")
+    return ke
+
+
+def assemble_hex8(p: Pattern, fmt: int, coords: torch.Tensor, material: torch.Tensor,
+                  values: torch.Tensor | None = None, accumulate: bool = False,
+                  stream=None) -> torch.Tensor:
+    """values := G with each hexahedron's stiffness computed inside the
+    row-owned assembly (no element matrices in memory; asynchronous)."""
+    _hex8_args(p, coords, material)
+    if values is None:
+        values = torch.empty(p.nnz, dtype=torch.float64, device=coords.device)
+    _require(values, torch.float64, "values")
+    if values.numel() < p.nnz:
+        raise ValueError(f"values must hold nnz = {p.nnz} entries")
+    _lib.check(_lib.load().assemble_hex8(p.handle, fmt, _ptr(coords), _ptr(material), _ptr(values),
+                                         ACCUMULATE if accumulate else 0, _stream(stream)),
+               "assemble_hex8")
+    return values
+
+
 RECIPE_LAPLACIAN = 0
 RECIPE_SPD = 1
 

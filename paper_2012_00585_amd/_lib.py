@@ -50,6 +50,8 @@ SIGNATURES = {
     "reassemble_values": (INT, [P, INT, P, P, INT, P]),
     "spmv_csr": (INT, [P, P, P, P, P]),
     "spmv_crac": (INT, [P, P, P, P, P]),
+    "hex8_element_matrices": (INT, [P, P, P, P, P]),
+    "assemble_hex8": (INT, [P, INT, P, P, P, INT, P]),
     "pattern_info": (INT, [P, PI64, PI64, PI64, PI32]),
     "pattern_arrays": (INT, [P, PP, PP, PP, PP]),
     "pattern_colouring": (INT, [P, PP, PP, PP]),

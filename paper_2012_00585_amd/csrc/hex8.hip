@@ -1,0 +1,343 @@
+// Element stiffness of 8-node trilinear hexahedra computed on the device --
+// the computation the paper replaces by a dummy matrix (Remark 1) -- either
+// written out as element matrices (hex8_element_matrices) or fused into the
+// row-owned assembly (assemble_hex8), which then reads node coordinates and
+// material parameters instead of an n x n matrix per element.
+//
+// Element: local nodes are the bottom face (zeta = -1) counter-clockwise
+// from (-1,-1), then the top face in the same order; N_a = (1 + xi_a xi)
+// (1 + eta_a eta)(1 + zeta_a zeta) / 8; 2x2x2 Gauss rule (points
+// +-1/sqrt(3), weights 1, xi fastest).  With J_ij = dx_i/dxi_j, C the
+// cofactor matrix of J and g_a,i = sum_j C_ij / det J * dN_a/dxi_j:
+//   d = 1 (Laplace, kappa):   K_ab = sum_q kappa (g_a . g_b) det J
+//   d = 3 (elasticity, lambda, mu), local DOF 3a + i:
+//     K_(a,i)(b,j) = sum_q [lambda g_a,i g_b,j + mu (g_a,j g_b,i + delta_ij g_a . g_b)] det J
+// Every quantity is evaluated as this sequence of correctly rounded
+// operations in this order (no fused multiply-add), so the matrices are the
+// same bits as any evaluation that keeps the order.
+//
+// Fused kernel: one 64-lane wavefront owns one node row, as the flat
+// row-owned kernel, and walks its incident elements in batches of 8.  Lane
+// (t, q) computes the geometry of entry t at quadrature point q into LDS,
+// lane (t, b) the d x d block of the owner's rows against element node b,
+// and the batch's row blocks are then added into the LDS accumulator entry
+// by entry, so every value receives its contributions in element order.
+#include <algorithm>
+
+#include "scatter_device.h"
+
+namespace feasm {
+namespace {
+
+using scatter::kCRAC;
+using scatter::kCSR;
+using scatter::row_lookup;
+
+constexpr double kGauss = 0.5773502691896258;  // the double nearest 1/sqrt(3), as 1.0/sqrt(3.0)
+
+struct Hex8Args {
+    const int32_t* conn;
+    const int64_t* inc_ptr;
+    const int32_t* inc_q;
+    const int32_t* row_ptr;
+    const int32_t* col_idx;
+    const int32_t* crac_row_ptr;
+    const int32_t* ca;
+    const double* coords;  // [n_nodes][3]
+    const double* mat;     // [n_elem][d == 1 ? 1 : 2]
+    double* values;
+    double* ke;  // element matrices (hex8_element_matrices)
+    int64_t n_nodes, n_elem;
+    int32_t acc_doubles, idx_ints;
+    int32_t accumulate;
+};
+
+// Reference corner a: (xi_a, eta_a, zeta_a) in {-1, 1}^3.
+__device__ inline double ref_coord(int a, int j) {
+    const int f = a & 3;
+    const bool plus = j == 0 ? (f == 1 || f == 2) : j == 1 ? (f >= 2) : (a >= 4);
+    return plus ? 1.0 : -1.0;
+}
+
+// Gradients g[a][i] and det J at quadrature point q of the element whose
+// node coordinates are x[3a + i].
+__device__ inline void hex8_point(const double* x, int q, double (&g)[8][3], double& det) {
+    const double xi[3] = {(q & 1) ? kGauss : -kGauss, (q & 2) ? kGauss : -kGauss,
+                          (q & 4) ? kGauss : -kGauss};
+    double dN[8][3];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        double f[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) f[j] = 1.0 + ref_coord(a, j) * xi[j];
+        dN[a][0] = ref_coord(a, 0) * f[1] * f[2] / 8.0;
+        dN[a][1] = f[0] * ref_coord(a, 1) * f[2] / 8.0;
+        dN[a][2] = f[0] * f[1] * ref_coord(a, 2) / 8.0;
+    }
+    double J[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a < 8; ++a) s = s + x[3 * a + i] * dN[a][j];
+            J[i][j] = s;
+        }
+    double C[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+            C[i][j] = J[i1][j1] * J[i2][j2] - J[i1][j2] * J[i2][j1];
+        }
+    det = J[0][0] * C[0][0] + J[0][1] * C[0][1] + J[0][2] * C[0][2];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) s = s + C[i][j] / det * dN[a][j];
+            g[a][i] = s;
+        }
+}
+
+// One quadrature term of the (a, b) block, added to blk (d*d values).
+template <int D>
+__device__ inline void hex8_block_term(const double* ga, const double* gb, double det,
+                                       const double* mat, double* blk) {
+    const double dot = ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2];
+    if (D == 1) {
+        blk[0] = blk[0] + mat[0] * dot * det;
+    } else {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const double t1 = mat[0] * ga[i] * gb[j] * det;
+                const double t2 = mat[1] * ga[j] * gb[i] * det;
+                const double t3 = i == j ? mat[1] * dot * det : 0.0;
+                blk[3 * i + j] = blk[3 * i + j] + (t1 + t2 + t3);
+            }
+    }
+}
+
+// LDS geometry of a batch of 8 (element, point) x 8 points: gradients and
+// det J per (t, q), [t][q][25].
+constexpr int kGeo = 25;
+
+// Lane (t = l / 8, q = l % 8): geometry of element e (if valid) at point q.
+__device__ inline void geometry_lane(const Hex8Args& A, int64_t e, int q, double* geo) {
+    double x[24];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        const int64_t v = A.conn[8 * e + a];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) x[3 * a + i] = A.coords[3 * v + i];
+    }
+    double g[8][3], det;
+    hex8_point(x, q, g, det);
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) geo[3 * a + i] = g[a][i];
+    geo[24] = det;
+}
+
+// The (a, b) block of element e summed over the 8 points, from the batch
+// geometry of its entry (geo_t: [8 points][kGeo]).
+template <int D>
+__device__ inline void block_from_geometry(const double* geo_t, int a, int b, const double* mat,
+                                           double (&blk)[D * D]) {
+#pragma unroll
+    for (int r = 0; r < D * D; ++r) blk[r] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const double* gq = geo_t + q * kGeo;
+        hex8_block_term<D>(gq + 3 * a, gq + 3 * b, gq[24], mat, blk);
+    }
+}
+
+// Element matrices: 8 elements per 64-lane block.
+template <int D>
+__global__ void __launch_bounds__(64) k_hex8_ke(Hex8Args A) {
+    __shared__ double geo[64 * kGeo];
+    constexpr int N = 8 * D, M = D == 1 ? 1 : 2;
+    const int l = threadIdx.x, t = l >> 3, s = l & 7;
+    const int64_t e0 = xcd_block(blockIdx.x, gridDim.x) * 8;
+    const int64_t e = e0 + t;
+    if (e < A.n_elem) geometry_lane(A, e, s, geo + l * kGeo);
+    __syncthreads();
+    // lane (a = t, b = s) of every element of the block
+    for (int te = 0; te < 8 && e0 + te < A.n_elem; ++te) {
+        const int64_t ee = e0 + te;
+        double mat[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) mat[m] = A.mat[M * ee + m];
+        double blk[D * D];
+        block_from_geometry<D>(geo + te * 8 * kGeo, t, s, mat, blk);
+        double* K = A.ke + ee * (int64_t)N * N;
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) K[(int64_t)(D * t + i) * N + D * s + j] = blk[D * i + j];
+    }
+}
+
+// Fused: one node row per wavefront.
+template <int FMT, int D>
+__global__ void __launch_bounds__(64) k_hex8_fused(Hex8Args A) {
+    constexpr int N = 8 * D, DN = D * N, M = D == 1 ? 1 : 2;
+    extern __shared__ double lds[];
+    double* geo = lds;                      // [64][kGeo]
+    double* slab = geo + 64 * kGeo;         // [8 entries][D rows][N]
+    double* acc = slab + 8 * DN;            // [D rows][ncols]
+    int32_t* sidx = reinterpret_cast<int32_t*>(acc + A.acc_doubles);
+    int32_t* scol = sidx + A.idx_ints;      // [8 entries][8 nodes]
+    const int l = threadIdx.x, t = l >> 3, s = l & 7;
+    const int64_t v = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t tbeg = A.inc_ptr[v], T = A.inc_ptr[v + 1] - tbeg;
+    const int32_t Rw = D * (int32_t)v;
+    int32_t rs, ncols, npairs = 0;
+    if (FMT == kCSR) {
+        rs = A.row_ptr[Rw];
+        ncols = A.row_ptr[Rw + 1] - rs;
+        for (int x = l; x < ncols; x += 64) sidx[x] = A.col_idx[rs + x];
+    } else {
+        const int32_t pb = A.crac_row_ptr[Rw], pe = A.crac_row_ptr[Rw + 1];
+        npairs = (pe - pb) >> 1;
+        rs = npairs > 0 ? A.ca[pb + 1] : 0;
+        ncols = npairs > 0 ? A.ca[pe + 1] - rs : 0;
+        if (npairs > 0)
+            for (int x = l; x < 2 * npairs + 2; x += 64) sidx[x] = A.ca[pb + x];
+    }
+    for (int x = l; x < D * ncols; x += 64) acc[x] = 0.0;
+    __syncthreads();
+    for (int64_t t0 = 0; t0 < T; t0 += 8) {
+        // lane (t, s): geometry of entry t at point s, and the column offset
+        // of element node s in the owned row
+        const bool valid = t0 + t < T;
+        int32_t q = 0;
+        if (valid) {
+            q = A.inc_q[tbeg + t0 + t];
+            const int64_t e = q >> 3;
+            geometry_lane(A, e, s, geo + l * kGeo);
+            scol[l] = row_lookup<FMT>(sidx, ncols, npairs, rs, D * A.conn[8 * e + s]);
+        }
+        __syncthreads();
+        // lane (t, s): the (a, s) block of entry t into the slab
+        if (valid) {
+            const int64_t e = q >> 3;
+            const int a = q & 7;
+            double mat[M];
+#pragma unroll
+            for (int m = 0; m < M; ++m) mat[m] = A.mat[M * e + m];
+            double blk[D * D];
+            block_from_geometry<D>(geo + t * 8 * kGeo, a, s, mat, blk);
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int j = 0; j < D; ++j) slab[t * DN + i * N + D * s + j] = blk[D * i + j];
+        }
+        __syncthreads();
+        // entry by entry, in element order
+        const int nt = (int)std::min<int64_t>(8, T - t0);
+        for (int te = 0; te < nt; ++te) {
+            for (int x = l; x < DN; x += 64) {
+                const int c1 = x / N, col = x - c1 * N, b = col / D, c = col - b * D;
+                const int32_t off = scol[te * 8 + b];
+                if (off >= 0) atomicAdd(acc + c1 * ncols + off + c, slab[te * DN + x]);
+            }
+        }
+        __syncthreads();
+    }
+    double* out = A.values + rs;
+    if (A.accumulate)
+        for (int x = l; x < D * ncols; x += 64) out[x] += acc[x];
+    else
+        for (int x = l; x < D * ncols; x += 64) out[x] = acc[x];
+}
+
+int check_hex8(const feasm_pattern* p, const double* coords, const double* material,
+               const std::string& who) {
+    if (!p) FEASM_FAIL(FEASM_EINVAL, who + ": null handle");
+    if (p->k != 8) FEASM_FAIL(FEASM_EINVAL, who + ": elements must have 8 nodes");
+    if (p->d != 1 && p->d != 3) FEASM_FAIL(FEASM_EINVAL, who + ": d must be 1 or 3");
+    if (!coords || !material) FEASM_FAIL(FEASM_EINVAL, who + ": null coords or material");
+    return FEASM_OK;
+}
+
+Hex8Args hex8_args(const feasm_pattern* p, const double* coords, const double* material) {
+    Hex8Args A{};
+    A.conn = p->conn;
+    A.inc_ptr = p->inc_ptr;
+    A.inc_q = p->inc_q;
+    A.row_ptr = p->row_ptr;
+    A.col_idx = p->col_idx;
+    A.crac_row_ptr = p->crac_row_ptr;
+    A.ca = p->ca;
+    A.coords = coords;
+    A.mat = material;
+    A.n_nodes = p->n_nodes;
+    A.n_elem = p->n_elem;
+    return A;
+}
+
+}  // namespace
+}  // namespace feasm
+
+extern "C" int hex8_element_matrices(const feasm_pattern* p, const double* coords,
+                                     const double* material, double* ke, hipStream_t stream) {
+    using namespace feasm;
+    int rc = check_hex8(p, coords, material, "hex8_element_matrices");
+    if (rc != FEASM_OK) return rc;
+    if (!ke) FEASM_FAIL(FEASM_EINVAL, "hex8_element_matrices: null ke");
+    if (p->n_elem == 0) return FEASM_OK;
+    Hex8Args A = hex8_args(p, coords, material);
+    A.ke = ke;
+    const unsigned blocks = (unsigned)ceil_div(p->n_elem, 8);
+    if (p->d == 1)
+        k_hex8_ke<1><<<blocks, 64, 0, stream>>>(A);
+    else
+        k_hex8_ke<3><<<blocks, 64, 0, stream>>>(A);
+    FEASM_HIP(hipGetLastError());
+    return FEASM_OK;
+}
+
+extern "C" int assemble_hex8(const feasm_pattern* p, int fmt, const double* coords,
+                             const double* material, double* values, int flags,
+                             hipStream_t stream) {
+    using namespace feasm;
+    int rc = check_hex8(p, coords, material, "assemble_hex8");
+    if (rc != FEASM_OK) return rc;
+    if (!values) FEASM_FAIL(FEASM_EINVAL, "assemble_hex8: null values");
+    if (fmt != FEASM_FMT_CSR && fmt != FEASM_FMT_CRAC)
+        FEASM_FAIL(FEASM_EINVAL, "assemble_hex8: fmt must be FEASM_FMT_CSR or FEASM_FMT_CRAC");
+    if (fmt == FEASM_FMT_CSR && !(p->flags & FEASM_BUILD_CSR))
+        FEASM_FAIL(FEASM_EINVAL, "assemble_hex8: handle was built without CSR");
+    if (fmt == FEASM_FMT_CRAC && !(p->flags & FEASM_BUILD_CRAC))
+        FEASM_FAIL(FEASM_EINVAL, "assemble_hex8: handle was built without CRAC");
+    if ((flags & ~FEASM_ACCUMULATE) != 0) FEASM_FAIL(FEASM_EINVAL, "assemble_hex8: unknown flag");
+    if (p->n_nodes == 0) return FEASM_OK;
+    Hex8Args A = hex8_args(p, coords, material);
+    A.values = values;
+    A.accumulate = (flags & FEASM_ACCUMULATE) ? 1 : 0;
+    const int d = p->d;
+    A.acc_doubles = d * d * p->max_deg;
+    A.idx_ints = fmt == FEASM_FMT_CSR ? d * p->max_deg : 2 * p->max_deg + 2;
+    const size_t lds = sizeof(double) * (64 * kGeo + 8 * d * 8 * d + (size_t)A.acc_doubles) +
+                       sizeof(int32_t) * ((size_t)A.idx_ints + 64);
+    if (lds > 64 * 1024)
+        FEASM_FAIL(FEASM_ELIMIT, "assemble_hex8: node rows too long for the LDS accumulator");
+    const unsigned blocks = (unsigned)p->n_nodes;
+    if (fmt == FEASM_FMT_CSR)
+        d == 1 ? k_hex8_fused<kCSR, 1><<<blocks, 64, lds, stream>>>(A)
+               : k_hex8_fused<kCSR, 3><<<blocks, 64, lds, stream>>>(A);
+    else
+        d == 1 ? k_hex8_fused<kCRAC, 1><<<blocks, 64, lds, stream>>>(A)
+               : k_hex8_fused<kCRAC, 3><<<blocks, 64, lds, stream>>>(A);
+    FEASM_HIP(hipGetLastError());
+    return FEASM_OK;
+}

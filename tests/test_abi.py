@@ -83,6 +83,9 @@ def test_numeric_calls_reject_null_handle(lib):
     assert lib.spmv_csr(None, d, d, d, None) == -1
     assert b"spmv_csr: null handle" in lib.last_error()
     assert lib.spmv_crac(None, d, d, d, None) == -1
+    assert lib.hex8_element_matrices(None, d, d, d, None) == -1
+    assert lib.assemble_hex8(None, 1, d, d, d, 0, None) == -1
+    assert b"assemble_hex8: null handle" in lib.last_error()
     lib.pattern_free(None)  # ignored
 
 
