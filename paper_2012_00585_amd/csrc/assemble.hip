@@ -60,7 +60,8 @@ __global__ void __launch_bounds__(64) k_owner(OwnArgs A) {
 template <int FMT, int D, int N, int B, int MODE>
 __global__ void __launch_bounds__(64) k_owner_pipe(OwnArgs A) {
     extern __shared__ double lds_d[];
-    owner_pipe_row<FMT, D, N, B, MODE>(A, xcd_block(blockIdx.x, gridDim.x), lds_d);
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    owner_pipe_row<FMT, D, N, B, MODE>(A, A.node_list ? A.node_list[blk] : blk, lds_d);
 }
 
 template <int FMT, int R, int J, int B>
@@ -147,6 +148,33 @@ int launch_owner_f(const feasm_pattern* p, OwnArgs& A, hipStream_t s) {
     // several rows per wavefront.)  By default (setting 0) they are used wherever they are
     // compiled, with B = 4 for rows of more than 192 values, else 8 where no
     // node has more incident entries, else 16.
+    if (p->tune_owner_flat == 0 && sh.g == 64 && p->node_order && p->max_inc > kLightInc &&
+        ((p->d == 3 && p->n == 24) || (p->d == 3 && p->n == 30))) {
+        // Light rows (at most 8 entries) with the single-batch kernel, the
+        // others with batches of 16, over the handle's node order.
+        const size_t lds8 = (size_t)A.group_bytes + (size_t)2 * 8 * p->k * 4;
+        const size_t lds16 = (size_t)A.group_bytes + (size_t)2 * 16 * p->k * 4;
+        if (lds16 <= 64 * 1024) {
+            const int64_t nl = p->n_light, nh = p->n_nodes - p->n_light;
+            OwnArgs L = A, H = A;
+            L.node_list = p->node_order;
+            H.node_list = p->node_order + nl;
+#define FEASM_SPLIT(DD, NN)                                                             \
+    if (p->d == DD && p->n == NN) {                                                    \
+        if (nl > 0) k_owner_pipe<FMT, DD, NN, 8, 0><<<(unsigned)nl, 64, lds8, s>>>(L);  \
+        if (nh > 0) {                                                                  \
+            if (p->tune_owner_prefetch)                                                \
+                k_owner_pipe<FMT, DD, NN, 16, 2><<<(unsigned)nh, 64, lds16, s>>>(H);   \
+            else                                                                       \
+                k_owner_pipe<FMT, DD, NN, 16, 1><<<(unsigned)nh, 64, lds16, s>>>(H);   \
+        }                                                                              \
+        FEASM_HIP(hipGetLastError());                                                   \
+        return FEASM_OK;                                                                \
+    }
+            FEASM_SPLIT(3, 24) FEASM_SPLIT(3, 30)
+#undef FEASM_SPLIT
+        }
+    }
     if (p->tune_owner_flat >= 0 && sh.g == 64) {
         const int dn = p->d * p->n;
         const int B = p->tune_owner_flat > 0 ? p->tune_owner_flat
@@ -155,6 +183,8 @@ int launch_owner_f(const feasm_pattern* p, OwnArgs& A, hipStream_t s) {
                                              : 16;
         const size_t lds = (size_t)A.group_bytes + (size_t)2 * B * p->k * 4;
         if (lds <= 64 * 1024) {
+            // node id order: each XCD takes a contiguous block range, which
+            // stays balanced only while light and heavy rows are mixed
             const unsigned blocks = (unsigned)p->n_nodes;
 #define FEASM_PIPE(DD, NN, BB)                                                          \
     if (p->d == DD && p->n == NN && B == BB) {                                         \

@@ -41,6 +41,8 @@ struct OffsetCache;  // value-only re-assembly lookup cache (assemble.hip)
 
 // Entries of padding after the incidence array (zeros).
 constexpr int kIncPad = 64;
+// Incident entries of a "light" node row (one batch of the flat row-owned kernel).
+constexpr int kLightInc = 8;
 
 struct feasm_pattern {
     int device = 0;
@@ -84,6 +86,10 @@ struct feasm_pattern {
     int32_t* elem_colour = nullptr;   // dev [n_elem]
 
     feasm::OffsetCache* cache = nullptr;
+    // nodes with at most kLightInc incident entries first, then the rest,
+    // each part in increasing id
+    int32_t* node_order = nullptr;  // dev [n_nodes]
+    int64_t n_light = 0;
     int32_t* owner_map = nullptr;  // dev [n_elem*k][k]: row-owned lookup record
     bool owner_map_valid = false;
 
@@ -108,6 +114,9 @@ __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + 
 int64_t scan_scratch_elems(int64_t n);
 template <typename T>
 int exclusive_scan(const T* in, int64_t n, int64_t* out, int64_t* scratch, hipStream_t s);
+// Builds p->node_order (see feasm_pattern) and its count of light nodes;
+// synchronises s.
+int build_node_order(feasm_pattern* p, hipStream_t s, int64_t* n_light_host);
 
 // Colouring (colour.hip): fills p->elem_colour, colour_elems, colour_ptr, n_colours.
 int build_colouring(feasm_pattern* p, hipStream_t s);

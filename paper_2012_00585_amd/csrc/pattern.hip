@@ -449,8 +449,13 @@ int build(feasm_pattern* p, const int32_t* conn_in, hipStream_t s) {
     k_close<<<1, 64, 0, s>>>(p->n_rows, p->nnz, p->n_ca - 2, p->row_ptr, p->crac_row_ptr, p->ca);
     FEASM_HIP(hipGetLastError());
 
+    // 6. node order for the row-owned kernels
+    int64_t n_light = nn;
+    TRY(build_node_order(p, s, &n_light));
+
     if (p->flags & FEASM_BUILD_COLOUR) TRY(build_colouring(p, s));
     FEASM_HIP(hipStreamSynchronize(s));
+    p->n_light = n_light;
     return FEASM_OK;
 }
 
@@ -460,7 +465,7 @@ void release_pattern(feasm_pattern* p) {
     void* arrs[] = {p->conn,    p->node_ptr,     p->node_col, p->node_nruns, p->noderun_ptr,
                     p->inc_ptr, p->inc_q,        p->inc_elem, p->inc_local,
                     p->row_ptr,  p->col_idx,    p->crac_row_ptr,
-                    p->ca,      p->colour_elems, p->elem_colour};
+                    p->ca,      p->colour_elems, p->elem_colour, p->node_order};
     for (void* a : arrs)
         if (a) (void)hipFree(a);
     release_cache(p);

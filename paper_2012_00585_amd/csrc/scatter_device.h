@@ -227,6 +227,7 @@ struct OwnArgs {
     const int64_t* node_ptr;  // kMap: row starts and lengths from the node pattern
     const int32_t* map;       // kMap: per incidence entry t, map[t*k + b] = offset of
                               // element node b's first column in the owned row
+    const int32_t* node_list;  // optional: block i owns node node_list[i]
 };
 
 template <int FMT>
