@@ -174,3 +174,65 @@ def test_autotune_keeps_results(feasm, orc):
     b.free()
     for p in pats:
         p.free()
+
+
+def test_batch512_full_mix_sampled(feasm, orc):
+    """The full 512-mesh mix in the launch configurations the benchmark
+    times (autotuned handles; persistent and per-mesh-graph batches), with
+    element matrices from the device generator; sampled meshes are checked
+    against the oracle fed with the generator's host twin.  Row-owned meshes
+    must match bit for bit, the others within the value tolerance."""
+    from fe_inputs import configs
+    from paper_2012_00585_amd import autotune
+    from paper_2012_00585_amd.batch import Batch
+
+    dev = torch.device("cuda:0")
+    specs = configs.batch_mix()
+    say(f"[batch512] building {len(specs)} meshes")
+    flags = feasm.BUILD_CSR | feasm.BUILD_CRAC | feasm.BUILD_COLOUR
+    pats, kes, vals, meta = [], [], [], []
+    for sp in specs:
+        conn, nn = meshes.quad_mesh(sp.size) if sp.kind == "quad" else meshes.hex_mesh(sp.size)
+        p = feasm.pattern_build(torch.from_numpy(conn).to(dev), sp.dofs_per_node, nn, flags)
+        recipe = feasm.RECIPE_LAPLACIAN if sp.kind == "quad" else feasm.RECIPE_SPD
+        kes.append(feasm.generate_ke(recipe, p.n_elem, p.n, sp.seed))
+        vals.append(torch.empty(p.nnz, dtype=torch.float64, device=dev))
+        pats.append(p)
+        meta.append((sp, conn, nn))
+    torch.cuda.synchronize()
+    autotune.autotune(pats, kes, vals, feasm.FMT_CRAC, reps=2, warmup=1, log=say)
+    # sampled: the smallest and the largest of each kind, and two in between
+    by_size = sorted(range(len(specs)), key=lambda i: (specs[i].kind, pats[i].n_elem))
+    quads = [i for i in by_size if specs[i].kind == "quad"]
+    hexes = [i for i in by_size if specs[i].kind == "hex"]
+    sample = sorted({quads[0], quads[len(quads) // 2], quads[-1], hexes[0], hexes[len(hexes) // 2],
+                     hexes[-1]})
+    refs = {}
+    for i in sample:
+        sp, conn, nn = meta[i]
+        E, k = conn.shape
+        n = k * sp.dofs_per_node
+        twin = philox.ke_laplacian if sp.kind == "quad" else philox.ke_spd
+        ke = twin(E, n, sp.seed)
+        rp, ci = orc.pattern(conn, sp.dofs_per_node, nn)
+        refs[i] = orc.assemble(conn, sp.dofs_per_node, ke, rp, ci)
+    paths = None  # each mesh's kernel path, from the persistent batch
+    for per_mesh_graph in (False, True):
+        say(f"[batch512] per_mesh_graph={per_mesh_graph}")
+        for v in vals:
+            v.fill_(np.nan)
+        b = Batch(pats, fmt=feasm.FMT_CRAC, per_mesh_graph=per_mesh_graph)
+        b.assemble(kes, vals)
+        torch.cuda.synchronize()
+        if paths is None:
+            paths = b.info()["paths"]
+        for i in sample:
+            got = _np(vals[i])
+            ov, oa = refs[i]
+            if paths[i].startswith(("own", "rows")):  # row-owned: element order
+                assert (got == ov).all(), (i, specs[i], per_mesh_graph)
+            else:
+                assert_values_close(got, ov, oa, what=f"mesh {i} {specs[i]}")
+        b.free()
+    for p in pats:
+        p.free()
