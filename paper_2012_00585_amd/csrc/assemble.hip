@@ -15,6 +15,15 @@
 //   4. add every K_e(r, s) at rowstart(r) + offset(row node, run of s) + the
 //      position of s inside its run: a hardware FP64 atomic add, or a plain
 //      read-modify-write when the launch covers one colour.
+//
+// The row-owned strategy (the default) instead gives each node's d DOF rows
+// to one wavefront, which walks the node's incident elements in element
+// order, adds their row slabs into an LDS accumulator and writes the rows
+// once (the static form of the paper's row-exclusive spin_int methods,
+// Sections 3.2-3.3; device code in scatter_device.h).  launch_owner picks
+// the kernel: the flat single-row kernels (k_owner_pipe) for the element
+// shapes they are compiled for, else several rows per wavefront
+// (k_owner_rows) or several lane groups per wavefront (k_owner).
 #include <algorithm>
 #include <climits>
 #include <new>
@@ -140,18 +149,18 @@ int launch_owner_f(const feasm_pattern* p, OwnArgs& A, hipStream_t s) {
     A.idx_ints = FMT == kMap ? 0 : FMT == kCSR ? p->d * p->max_deg : 2 * p->max_deg + 2;
     A.acc_doubles = p->d * p->d * p->max_deg;
     A.group_bytes = sh.group_bytes;
-    // Flat, pipelined batches: one node row per wavefront, B entries per
-    // batch, for the element shapes they are compiled for: 8-node hexes and
-    // 10-node tets with 3 DOFs per node (every mode), and, for rows of at most
-    // B entries, Q3/Q4 quads with 4 DOFs and Q1 quads with 4 to 8.  (High-order
-    // quads with 1 DOF, whose rows mostly have one entry, are faster with
-    // several rows per wavefront.)  By default (setting 0) they are used wherever they are
-    // compiled, with B = 4 for rows of more than 192 values, else 8 where no
-    // node has more incident entries, else 16.
+    // Flat batches: one node row per wavefront, B entries per batch, for the
+    // element shapes they are compiled for: 8-node hexes and 10-node tets
+    // with 3 DOFs per node (every mode), and, for rows of at most B entries,
+    // Q3/Q4 quads with 4 DOFs and Q1 quads with 4 to 8.  (High-order quads
+    // with 1 DOF, whose rows mostly have one entry, are faster with several
+    // rows per wavefront.)  By default (setting 0) they are used wherever
+    // they are compiled, with B = 4 for rows of more than 192 values, else 8
+    // where no node has more incident entries, else 16; meshes with heavier
+    // nodes run the light rows (at most 8 entries) and the rest as two
+    // launches over the handle's node order.
     if (p->tune_owner_flat == 0 && sh.g == 64 && p->node_order && p->max_inc > kLightInc &&
         ((p->d == 3 && p->n == 24) || (p->d == 3 && p->n == 30))) {
-        // Light rows (at most 8 entries) with the single-batch kernel, the
-        // others with batches of 16, over the handle's node order.
         const size_t lds8 = (size_t)A.group_bytes + (size_t)2 * 8 * p->k * 4;
         const size_t lds16 = (size_t)A.group_bytes + (size_t)2 * 16 * p->k * 4;
         if (lds16 <= 64 * 1024) {

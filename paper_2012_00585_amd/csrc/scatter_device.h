@@ -583,8 +583,10 @@ __device__ inline void owner_rows_tile(const OwnArgs& A, int64_t blk, double* ld
 // A batch's index loads (column nodes, or the recorded offsets) are issued
 // before its element-row loads, and the first batch's loads before the row's
 // own index words are staged, so a wavefront waits for memory about once per
-// batch rather than once per dependent load.  The incidence array is padded by kIncPad entries, which lets a batch's
-// element numbers be read with unconditional scalar loads.
+// batch rather than once per dependent load.  The incidence array is padded
+// by kIncPad entries, which lets a batch's element numbers be read with
+// unconditional scalar loads.
+
 // The lane id, hidden from the optimiser so that per-lane index arithmetic is
 // recomputed where it is used instead of being kept live across a loop.
 __device__ inline int opaque_lane() {
