@@ -255,8 +255,18 @@ int spmv_crac(const feasm_pattern* p, const double* values, const double* x, dou
  * g_a,i g_b,j + mu (g_a,j g_b,i + delta_ij g_a . g_b)] det J (local DOF
  * 3a + i), with the 2x2x2 Gauss rule (points +-1/sqrt(3), xi fastest), J_ij
  * = dx_i/dxi_j and g_a,i = sum_j C_ij / det J * dN_a/dxi_j (C: cofactors of
- * J).  Each entry is that sequence of correctly rounded operations in that
- * order (no fused multiply-add).
+ * J).  Each entry is one fixed sequence of correctly rounded operations and
+ * fused multiply-adds (fma(a,b,c) = a*b + c rounded once):
+ *   J_ij  = fma over a = 0..7 of (x_a,i, dN_a,j), from 0
+ *   C_ij  = fma(J_i1j1, J_i2j2, -(J_i1j2 * J_i2j1)), i1 = i+1, i2 = i+2 mod 3
+ *   det   = fma(J_00, C_00, fma(J_01, C_01, J_02 * C_02))
+ *   g_a,i = fma over j = 0..2 of (C_ij / det, dN_a,j), from 0
+ *   dot   = fma(g_a,2, g_b,2, fma(g_a,1, g_b,1, g_a,0 * g_b,0))
+ *   d = 1: K_ab += (kappa * det) * dot
+ *   d = 3: l = lambda * det, m = mu * det; s = (i == j ? m * dot : 0);
+ *          s = fma(m * g_a,j, g_b,i, s); s = fma(l * g_a,i, g_b,j, s);
+ *          K_(a,i)(b,j) += s
+ * with the quadrature points summed in order.
  *   coords    dev double [n_nodes][3]
  *   material  dev double [n_elem] (kappa) for d = 1, [n_elem][2] (lambda,
  *             mu) for d = 3

@@ -12,9 +12,10 @@
 //   d = 1 (Laplace, kappa):   K_ab = sum_q kappa (g_a . g_b) det J
 //   d = 3 (elasticity, lambda, mu), local DOF 3a + i:
 //     K_(a,i)(b,j) = sum_q [lambda g_a,i g_b,j + mu (g_a,j g_b,i + delta_ij g_a . g_b)] det J
-// Every quantity is evaluated as this sequence of correctly rounded
-// operations in this order (no fused multiply-add), so the matrices are the
-// same bits as any evaluation that keeps the order.
+// Every quantity is evaluated as one fixed sequence of correctly rounded
+// operations and fused multiply-adds (stated at each step below and in the
+// header), so the matrices are the same bits as any evaluation that keeps
+// the sequence.
 //
 // Fused kernel: one 64-lane wavefront owns one node row, as the flat
 // row-owned kernel, and walks its incident elements in batches of 8.  Lane
@@ -74,6 +75,7 @@ __device__ inline void hex8_point(const double* x, int q, double (&g)[8][3], dou
         dN[a][1] = f[0] * ref_coord(a, 1) * f[2] / 8.0;
         dN[a][2] = f[0] * f[1] * ref_coord(a, 2) / 8.0;
     }
+    // J_ij: fused multiply-adds over a, from 0
     double J[3][3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -81,7 +83,7 @@ __device__ inline void hex8_point(const double* x, int q, double (&g)[8][3], dou
         for (int j = 0; j < 3; ++j) {
             double s = 0.0;
 #pragma unroll
-            for (int a = 0; a < 8; ++a) s = s + x[3 * a + i] * dN[a][j];
+            for (int a = 0; a < 8; ++a) s = fma(x[3 * a + i], dN[a][j], s);
             J[i][j] = s;
         }
     double C[3][3];
@@ -90,16 +92,16 @@ __device__ inline void hex8_point(const double* x, int q, double (&g)[8][3], dou
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
-            C[i][j] = J[i1][j1] * J[i2][j2] - J[i1][j2] * J[i2][j1];
+            C[i][j] = fma(J[i1][j1], J[i2][j2], -(J[i1][j2] * J[i2][j1]));
         }
-    det = J[0][0] * C[0][0] + J[0][1] * C[0][1] + J[0][2] * C[0][2];
+    det = fma(J[0][0], C[0][0], fma(J[0][1], C[0][1], J[0][2] * C[0][2]));
 #pragma unroll
     for (int a = 0; a < 8; ++a)
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             double s = 0.0;
 #pragma unroll
-            for (int j = 0; j < 3; ++j) s = s + C[i][j] / det * dN[a][j];
+            for (int j = 0; j < 3; ++j) s = fma(C[i][j] / det, dN[a][j], s);
             g[a][i] = s;
         }
 }
@@ -108,18 +110,19 @@ __device__ inline void hex8_point(const double* x, int q, double (&g)[8][3], dou
 template <int D>
 __device__ inline void hex8_block_term(const double* ga, const double* gb, double det,
                                        const double* mat, double* blk) {
-    const double dot = ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2];
+    const double dot = fma(ga[2], gb[2], fma(ga[1], gb[1], ga[0] * gb[0]));
     if (D == 1) {
-        blk[0] = blk[0] + mat[0] * dot * det;
+        blk[0] = blk[0] + (mat[0] * det) * dot;
     } else {
+        const double l = mat[0] * det, m = mat[1] * det;
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                const double t1 = mat[0] * ga[i] * gb[j] * det;
-                const double t2 = mat[1] * ga[j] * gb[i] * det;
-                const double t3 = i == j ? mat[1] * dot * det : 0.0;
-                blk[3 * i + j] = blk[3 * i + j] + (t1 + t2 + t3);
+                double s = i == j ? m * dot : 0.0;
+                s = fma(m * ga[j], gb[i], s);
+                s = fma(l * ga[i], gb[j], s);
+                blk[3 * i + j] = blk[3 * i + j] + s;
             }
     }
 }
