@@ -239,6 +239,8 @@ def main():
             "algorithmic_bytes": nbytes,
             "effective_GBps": nbytes / (t_full["mean"] * 1e-3) / 1e9,
             "scatter_GBps": nbytes / (t_sc["mean"] * 1e-3) / 1e9,
+            # the element matrices alone: the stream every strategy must read
+            "Ke_only_GBps": w.n_elem * w.n * w.n * 8 / (t_sc["mean"] * 1e-3) / 1e9,
         }
     log("[bench] value-only re-assembly latency")
     reasm = {}
@@ -331,6 +333,46 @@ def main():
     print(json.dumps(line), flush=True)
 
 
+def _oracle_mesh(spec):
+    """One mesh of the batch mix through the serial oracle (pattern, then
+    assembly); returns (elements, seconds).  The oracle's work does not
+    depend on the values, so the paper's all-ones dummy element stands in
+    for the generated matrices."""
+    from fe_inputs import matrices, meshes
+    from oracle import oracle
+
+    conn, nn = meshes.quad_mesh(spec.size) if spec.kind == "quad" else meshes.hex_mesh(spec.size)
+    E, k = conn.shape
+    d = spec.dofs_per_node
+    ke = matrices.ke_ones(E, k * d)
+    t0 = time.perf_counter()
+    rp, ci = oracle.pattern(conn, d, nn)
+    oracle.assemble(conn, d, ke, rp, ci, with_abs=False)
+    return E, time.perf_counter() - t0
+
+
+def batch_cpu_baseline(specs, count):
+    """The serial oracle on the first `count` meshes of the mix, one mesh per
+    process on every host core (independent meshes, no threading inside an
+    assembly); pattern + numeric phase."""
+    import multiprocessing as mp
+
+    sample = list(specs[:count])
+    cores = os.cpu_count() or 1
+    # fork: the workers never touch the GPU
+    with mp.get_context("fork").Pool(min(cores, len(sample))) as pool:
+        t0 = time.perf_counter()
+        res = pool.map(_oracle_mesh, sample, chunksize=1)
+        wall = time.perf_counter() - t0
+    E = sum(r[0] for r in res)
+    busy = sum(r[1] for r in res)
+    return {"value": E / wall, "unit": "element matrices/s", "cores": min(cores, len(sample)),
+            "kind": "oracle",
+            "sample": (f"first {len(sample)} meshes of the mix ({E} elements), one mesh per "
+                       f"process on {min(cores, len(sample))} host cores, pattern + numeric "
+                       f"phase; wall {wall:.1f} s, {busy:.1f} s of oracle work")}
+
+
 def bench_batch(args):
     """Many meshes in one persistent, graph-captured launch vs one launch per mesh."""
     import torch
@@ -421,6 +463,9 @@ def bench_batch(args):
     b.free()
     for p in pats:
         p.free()
+    if args.cpu_reps > 0:
+        log("[bench] CPU baseline (serial oracle, one mesh per process)")
+        line["cpu_baseline"] = batch_cpu_baseline(specs, 32)
     print(json.dumps(line), flush=True)
 
 
