@@ -152,6 +152,8 @@ def main():
                     help="batch512: number of meshes (the mix is the first N of the 512)")
     ap.add_argument("--cpu-reps", type=int, default=3, help="0 skips the oracle baseline")
     ap.add_argument("--only", default="", help="comma-separated variants to time (default: all)")
+    ap.add_argument("--hex8-pipe", type=int, default=0,
+                    help="hex8 workload: fused-kernel setting (0 auto, n blocks per CU, -1 off)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run 3 plain device copies of this many MiB (a known-size "
                          "reference for hardware byte counters)")
@@ -567,6 +569,10 @@ def bench_hex8(args):
         vals = torch.empty(p.nnz, dtype=torch.float64, device=dev)
         ke = torch.empty((E, p.n, p.n), dtype=torch.float64, device=dev)
         r = {}
+        p.tune(feasm.TUNE_HEX8_PIPE, -1)
+        r["fused_one_node_per_wave_crac_ms"] = stats(time_calls(
+            lambda: feasm.assemble_hex8(p, feasm.FMT_CRAC, x, mat, vals), reps, args.warmup))
+        p.tune(feasm.TUNE_HEX8_PIPE, args.hex8_pipe)
         for name, fmt in (("csr", feasm.FMT_CSR), ("crac", feasm.FMT_CRAC)):
             r[f"fused_{name}_ms"] = stats(time_calls(
                 lambda f=fmt: feasm.assemble_hex8(p, f, x, mat, vals), reps, args.warmup))
@@ -588,7 +594,8 @@ def bench_hex8(args):
         r["speedup_fused_vs_two_pass"] = r["two_pass_ms"]["mean"] / best
         r["nnz"] = p.nnz
         log(f"[bench] hex8 d={d}: fused csr {r['fused_csr_ms']['mean']:.3f} crac "
-            f"{r['fused_crac_ms']['mean']:.3f} ms; element matrices "
+            f"{r['fused_crac_ms']['mean']:.3f} ms (one node per wavefront "
+            f"{r['fused_one_node_per_wave_crac_ms']['mean']:.3f}); element matrices "
             f"{r['element_matrices_ms']['mean']:.3f} + assembly "
             f"{r['assembly_from_matrices_ms']['mean']:.3f} = two-pass "
             f"{r['two_pass_ms']['mean']:.3f} ms")

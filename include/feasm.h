@@ -210,6 +210,14 @@ int pattern_colouring(const feasm_pattern* p, const int64_t** colour_ptr,
  *                                   2048 (0: 1024, or 512 for CRAC with at most
  *                                   96 values per row on average); rows per
  *                                   wavefront follow
+ *   FEASM_TUNE_HEX8_PIPE            assemble_hex8: 0 = nodes with at most 8
+ *                                   incident entries by the pipelined kernel
+ *                                   (a grid the compute units hold at once,
+ *                                   each wavefront a contiguous range of
+ *                                   nodes), the rest one node per wavefront;
+ *                                   n in [1, 16] = the pipelined grid with n
+ *                                   blocks per compute unit; -1 = every node
+ *                                   one per wavefront
  * Returns EINVAL for an unknown key or value.
  */
 enum {
@@ -220,7 +228,8 @@ enum {
     FEASM_TUNE_STRATEGY = 5,
     FEASM_TUNE_OWNER_FLAT = 6,
     FEASM_TUNE_OWNER_PREFETCH = 7,
-    FEASM_TUNE_SPMV_CHUNK = 8
+    FEASM_TUNE_SPMV_CHUNK = 8,
+    FEASM_TUNE_HEX8_PIPE = 9
 };
 int pattern_tune(feasm_pattern* p, int key, int64_t value);
 

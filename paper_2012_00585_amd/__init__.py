@@ -37,6 +37,7 @@ TUNE_STRATEGY = 5
 TUNE_OWNER_FLAT = 6
 TUNE_OWNER_PREFETCH = 7
 TUNE_SPMV_CHUNK = 8
+TUNE_HEX8_PIPE = 9
 
 _HIP_D2D = 3  # hipMemcpyDeviceToDevice
 

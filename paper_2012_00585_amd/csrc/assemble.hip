@@ -561,6 +561,12 @@ extern "C" int pattern_tune(feasm_pattern* p, int key, int64_t value) {
         p->tune_spmv_chunk = (int32_t)value;
         return FEASM_OK;
     }
+    if (key == FEASM_TUNE_HEX8_PIPE) {
+        if (value < -1 || value > 16)
+            FEASM_FAIL(FEASM_EINVAL, "pattern_tune: hex8 pipeline must be -1, 0 or 1..16 blocks per CU");
+        p->tune_hex8_pipe = (int32_t)value;
+        return FEASM_OK;
+    }
     if (key == FEASM_TUNE_OWNER_PREFETCH) {
         if (value != 0 && value != 1)
             FEASM_FAIL(FEASM_EINVAL, "pattern_tune: owner prefetch must be 0 or 1");

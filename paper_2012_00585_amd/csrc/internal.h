@@ -102,6 +102,8 @@ struct feasm_pattern {
     int32_t tune_owner_flat = 0;           // flat batches: -1 off, 0 auto, else entries per batch
     int32_t tune_owner_prefetch = 0;       // flat batches: issue the next batch early
     int32_t tune_spmv_chunk = 0;           // matrix-vector product: values per LDS chunk
+    int32_t tune_hex8_pipe = 0;            // fused hexahedra: -1 one node per wavefront, 0 auto,
+                                           // else pipelined blocks per CU
 };
 
 namespace feasm {

@@ -49,6 +49,9 @@ MESHES = [
     ("hex3x2x5_jitter", lambda: (*meshes.hex_mesh(3, 2, 5),
                                  meshes.hex_coords(3, 2, 5, jitter=0.2, seed=2))),
     ("hex3_doubled", lambda: _doubled()),
+    ("hex6x5x4_permuted_isolated", lambda: _permuted_isolated()),
+    ("hex12x10x9_jitter", lambda: (*meshes.hex_mesh(12, 10, 9),
+                                   meshes.hex_coords(12, 10, 9, jitter=0.25, seed=4))),
 ]
 
 
@@ -57,6 +60,23 @@ def _doubled():
     the fused kernel walks more than one batch per row."""
     conn, nn = meshes.hex_mesh(3)
     return np.concatenate([conn, conn[::-1]]), nn, meshes.hex_coords(3, jitter=0.2, seed=3)
+
+
+def _permuted_isolated():
+    """Relabelled nodes (the node order is no longer the geometric order)
+    plus two nodes no element uses (rows without entries)."""
+    conn, nn = meshes.hex_mesh(6, 5, 4)
+    x = meshes.hex_coords(6, 5, 4, jitter=0.2, seed=6)
+    perm = np.random.default_rng(7).permutation(nn + 2)
+    xp = np.zeros((nn + 2, 3))
+    xp[perm[:nn]] = x
+    return perm[conn].astype(np.int32), nn + 2, xp
+
+
+# fused kernel settings: 0 = pipelined light nodes (grid from occupancy),
+# 1 = pipelined with one block per compute unit (several nodes per wavefront
+# on the larger meshes), -1 = one node per wavefront everywhere
+PIPE = [0, 1, -1]
 
 
 @pytest.mark.parametrize("d", [1, 3])
@@ -70,12 +90,15 @@ def test_element_matrices_and_fused_assembly_bit_exact(feasm, orc, name, make, d
     assert (kd == K).all()
     rp, ci = orc.pattern(conn, d, nn)
     ov, _ = orc.assemble(conn, d, K, rp, ci)
-    for fmt in (feasm.FMT_CSR, feasm.FMT_CRAC):
-        v = _np(feasm.assemble_hex8(p, fmt, xd, md))
-        assert (v == ov).all(), fmt
-        acc = torch.full((p.nnz,), 2.0, dtype=torch.float64, device="cuda")
-        feasm.assemble_hex8(p, fmt, xd, md, acc, accumulate=True)
-        assert (_np(acc) == ov + 2.0).all()
+    for pipe in PIPE:
+        p.tune(feasm.TUNE_HEX8_PIPE, pipe)
+        for fmt in (feasm.FMT_CSR, feasm.FMT_CRAC):
+            say(f"[hex8] {name} d={d} pipe={pipe} fmt={fmt}")
+            v = _np(feasm.assemble_hex8(p, fmt, xd, md))
+            assert (v == ov).all(), (pipe, fmt)
+            acc = torch.full((p.nnz,), 2.0, dtype=torch.float64, device="cuda")
+            feasm.assemble_hex8(p, fmt, xd, md, acc, accumulate=True)
+            assert (_np(acc) == ov + 2.0).all(), (pipe, fmt)
     p.free()
 
 
@@ -88,11 +111,26 @@ def test_hex64_elasticity_full_size(feasm, orc):
     K, _ = orc.hex8_matrices(conn, x, 3, mat, with_abs=False)
     rp, ci = orc.pattern(conn, 3, nn)
     ov, _ = orc.assemble(conn, 3, K, rp, ci, with_abs=False)
-    v = _np(feasm.assemble_hex8(p, feasm.FMT_CRAC, xd, md))
-    assert (v == ov).all()
+    for pipe in PIPE:
+        say(f"[hex8] 64^3 elasticity pipe={pipe}")
+        p.tune(feasm.TUNE_HEX8_PIPE, pipe)
+        v = _np(feasm.assemble_hex8(p, feasm.FMT_CRAC, xd, md))
+        assert (v == ov).all(), pipe
+    p.tune(feasm.TUNE_HEX8_PIPE, 0)
+    assert (_np(feasm.assemble_hex8(p, feasm.FMT_CSR, xd, md)) == ov).all()
     # the two-pass path gives the same values
     kd = feasm.hex8_element_matrices(p, xd, md)
     assert (_np(feasm.assemble_crac(p, kd, scatter=feasm.SCATTER_OWNER)) == ov).all()
+    p.free()
+
+
+def test_pipeline_setting_range(feasm):
+    dev = torch.device("cuda:0")
+    conn, nn = meshes.hex_mesh(2)
+    p = feasm.pattern_build(torch.from_numpy(conn).to(dev), 1, nn)
+    for bad in (-2, 17):
+        with pytest.raises(feasm.FeasmError):
+            p.tune(feasm.TUNE_HEX8_PIPE, bad)
     p.free()
 
 
