@@ -351,7 +351,7 @@ __global__ void __launch_bounds__(64) k_hex8_fused(Hex8Args A) {
     if (A.accumulate)
         for (int x = l; x < D * ncols; x += 64) out[x] += acc[x];
     else
-        for (int x = l; x < D * ncols; x += 64) out[x] = acc[x];
+        for (int x = l; x < D * ncols; x += 64) __builtin_nontemporal_store(acc[x], out + x);
 }
 
 // Pipelined fused kernel over the light nodes (at most 8 incident entries,
@@ -537,7 +537,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) k_
         if (A.accumulate)
             for (int x = l; x < D * ncols; x += 64) out[x] += acc[x];
         else
-            for (int x = l; x < D * ncols; x += 64) out[x] = acc[x];
+            for (int x = l; x < D * ncols; x += 64) __builtin_nontemporal_store(acc[x], out + x);
         __syncthreads();
 
         // advance the stages

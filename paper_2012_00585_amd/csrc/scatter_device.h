@@ -409,7 +409,7 @@ __device__ inline void owner_tiles(const OwnArgs& A, int64_t first, int64_t last
             if (A.accumulate)
                 for (int x = l; x < d * ncols; x += G) out[x] += acc[x];
             else
-                for (int x = l; x < d * ncols; x += G) out[x] = acc[x];
+                for (int x = l; x < d * ncols; x += G) __builtin_nontemporal_store(acc[x], out + x);
         }
         __syncthreads();
     }
@@ -564,7 +564,7 @@ __device__ inline void owner_rows_tile(const OwnArgs& A, int64_t blk, double* ld
             if (A.accumulate)
                 for (int x = l; x < d * ncols[r]; x += 64) out[x] += acc[x];
             else
-                for (int x = l; x < d * ncols[r]; x += 64) out[x] = acc[x];
+                for (int x = l; x < d * ncols[r]; x += 64) __builtin_nontemporal_store(acc[x], out + x);
         }
     }
 }
@@ -751,7 +751,7 @@ __device__ inline void owner_pipe_row(const OwnArgs& A, int64_t v, double* lds_d
     if (A.accumulate)
         for (int x = l; x < D * ncols; x += 64) out[x] += acc[x];
     else
-        for (int x = l; x < D * ncols; x += 64) out[x] = acc[x];
+        for (int x = l; x < D * ncols; x += 64) __builtin_nontemporal_store(acc[x], out + x);
 }
 
 // Records, for every incidence entry t of node v and every element node b,
