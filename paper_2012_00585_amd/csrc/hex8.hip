@@ -256,8 +256,12 @@ __device__ inline void block_from_point_data(const double* cd_t, const double* d
 // Element matrices: 8 elements per 64-lane block.
 template <int D>
 __global__ void __launch_bounds__(64) k_hex8_ke(Hex8Args A) {
-    __shared__ double geo[64 * kGeo];
     constexpr int N = 8 * D, M = D == 1 ? 1 : 2;
+    __shared__ double geo[64 * kGeo];
+    // one element matrix, written out by consecutive lanes so that every
+    // store instruction covers whole cache lines (non-temporal stores are
+    // not merged across instructions)
+    __shared__ double slab[N * N];
     const int l = threadIdx.x, t = l >> 3, s = l & 7;
     const int64_t e0 = xcd_block(blockIdx.x, gridDim.x) * 8;
     const int64_t e = e0 + t;
@@ -271,11 +275,15 @@ __global__ void __launch_bounds__(64) k_hex8_ke(Hex8Args A) {
         for (int m = 0; m < M; ++m) mat[m] = A.mat[M * ee + m];
         double blk[D * D];
         block_from_geometry<D>(geo + te * 8 * kGeo, t, s, mat, blk);
-        double* K = A.ke + ee * (int64_t)N * N;
 #pragma unroll
         for (int i = 0; i < D; ++i)
 #pragma unroll
-            for (int j = 0; j < D; ++j) K[(int64_t)(D * t + i) * N + D * s + j] = blk[D * i + j];
+            for (int j = 0; j < D; ++j) slab[(D * t + i) * N + D * s + j] = blk[D * i + j];
+        __syncthreads();
+        double* K = A.ke + ee * (int64_t)N * N;
+#pragma unroll
+        for (int u = 0; u < N * N / 64; ++u) __builtin_nontemporal_store(slab[64 * u + l], K + 64 * u + l);
+        __syncthreads();
     }
 }
 
