@@ -357,6 +357,28 @@ void batch_free(feasm_batch* b);
 const char* last_error(void);
 
 /*
+ * Device allocator of the library (for the caller's memory pool, e.g. a
+ * framework's caching allocator).  Every device array the library creates
+ * from then on -- pattern arrays, the re-assembly lookup record and cache,
+ * batch tables, serving buffers and the temporaries of pattern_build --
+ * comes from alloc(bytes, stream, ctx), which returns device memory of the
+ * current device, aligned to at least 256 bytes and usable in stream order
+ * on `stream`, or NULL when it cannot (the library call then fails with
+ * FEASM_ENOMEM).  The library gives each array back with
+ * release(ptr, stream, ctx) once no work of its own uses it any longer
+ * (stream may be NULL when the release happens outside a stream, as in
+ * pattern_free).  An object remembers the allocator that created it and
+ * releases its arrays through that one, whatever is set later.  Both NULL
+ * restores the default, hipMalloc / hipFree; exactly one NULL is EINVAL.
+ * Process-wide; the callbacks may be called from any thread that calls the
+ * library.  Unlike every other entry point it is not tied to a pattern or
+ * to the paper: it is the library's memory-ownership hook.
+ */
+typedef void* (*feasm_alloc_fn)(size_t bytes, hipStream_t stream, void* ctx);
+typedef void (*feasm_release_fn)(void* ptr, hipStream_t stream, void* ctx);
+int set_allocator(feasm_alloc_fn alloc, feasm_release_fn release, void* ctx);
+
+/*
  * Serving engine: requests for one assembly followed by n_reassembly
  * value-only re-assemblies of a registered mesh (whose pattern stays
  * resident), each iteration with fresh element matrices from generate_ke

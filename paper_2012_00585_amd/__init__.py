@@ -11,7 +11,9 @@ are torch CUDA (HIP) tensors; streams default to torch's current stream.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
+import weakref
 
 import torch
 
@@ -83,6 +85,7 @@ class Pattern:
         self.nnz = nnz.value
         self.n_ca = n_ca.value
         self.n_colours = n_col.value
+        _track(self)
 
     @property
     def handle(self):
@@ -298,3 +301,61 @@ def generate_ke(recipe: int, n_elem: int, n: int, seed: int, elem_offset: int = 
 def load():
     """Load the native library (raises if it is not built)."""
     return _lib.load()
+
+
+# ------------------------------------------------------------ device memory
+# Objects that own device arrays (patterns, batches); freed at interpreter
+# exit while the allocator that created their arrays is still usable.
+_live = weakref.WeakSet()
+_allocator_refs = None  # the ctypes callbacks installed last (kept alive)
+
+
+def _track(obj):
+    _live.add(obj)
+
+
+@atexit.register
+def _free_live_objects():
+    for obj in list(_live):
+        try:
+            obj.free()
+        except Exception:
+            pass
+
+
+def set_allocator(alloc=None, release=None, ctx=None):
+    """Install device-allocation callbacks for the library's own arrays.
+
+    ``alloc`` and ``release`` are ``_lib.ALLOC_FN`` / ``_lib.RELEASE_FN``
+    ctypes callbacks (or both None for hipMalloc/hipFree).  Objects keep the
+    allocator that created them."""
+    global _allocator_refs
+    if (alloc is None) != (release is None):
+        raise ValueError("give both alloc and release, or neither")
+    a = alloc if alloc is not None else _lib.ALLOC_FN()
+    r = release if release is not None else _lib.RELEASE_FN()
+    _lib.check(_lib.load().set_allocator(a, r, ctx), "set_allocator")
+    if alloc is not None:
+        # callbacks stay referenced while any object may still release through them
+        _allocator_refs = (alloc, release, _allocator_refs)
+
+
+def use_torch_allocator():
+    """Take the library's device arrays from torch's caching allocator, on
+    the stream of the call that needs them (the current device's)."""
+
+    def _alloc(nbytes, stream, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+        except Exception:
+            return None
+
+    def _release(ptr, stream, ctx):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    set_allocator(_lib.ALLOC_FN(_alloc), _lib.RELEASE_FN(_release))
+
+
+def use_default_allocator():
+    """Back to hipMalloc / hipFree for arrays created from now on."""
+    set_allocator()

@@ -43,6 +43,10 @@ class RequestResult(ctypes.Structure):
                 ("done_s", ctypes.c_double)]
 
 
+# set_allocator callbacks: alloc(bytes, stream, ctx) -> ptr, release(ptr, stream, ctx)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
 SIGNATURES = {
     "pattern_build": (INT, [P, I64, I32, I32, I64, U32, P, PP]),
     "assemble_csr": (INT, [P, P, P, INT, P]),
@@ -65,6 +69,7 @@ SIGNATURES = {
     "serve_run": (INT, [P, P, I64, ctypes.POINTER(Request), I64, INT, I32, I64,
                         ctypes.POINTER(RequestResult), P]),
     "last_error": (ctypes.c_char_p, []),
+    "set_allocator": (INT, [ALLOC_FN, RELEASE_FN, P]),
 }
 
 _lib = None

@@ -14,7 +14,7 @@ import ctypes
 
 import torch
 
-from . import FMT_CRAC, Pattern, _lib, _require, _stream
+from . import FMT_CRAC, Pattern, _lib, _require, _stream, _track
 
 PATH_NAMES = ["own_g4", "own_g8", "own_g16", "own_g32", "own_g64_j1", "own_g64_j2", "own_g64_j4",
               "own_g64_j8", "own_g64_j16", "rows2_j1", "rows2_j2", "elem_atomic16", "elem_atomic32",
@@ -34,6 +34,7 @@ class Batch:
         self._h = h
         self.fmt = fmt
         self._keep = None
+        _track(self)
 
     def assemble(self, kes, values, stream=None):
         """Replay the batch graph; kes[i], values[i] are device float64 tensors."""
@@ -64,6 +65,7 @@ class Batch:
         if self._h is not None:
             _lib.load().batch_free(self._h)
             self._h = None
+        self._keep = None
 
     def __del__(self):
         try:

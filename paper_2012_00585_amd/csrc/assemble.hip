@@ -436,14 +436,14 @@ int assemble_on_stream(const feasm_pattern* p, int fmt, const double* ke, double
 }
 
 void release_owner_map(feasm_pattern* p) {
-    if (p->owner_map) (void)hipFree(p->owner_map);
+    dev_free(p->alloc, p->owner_map, nullptr);
     p->owner_map = nullptr;
     p->owner_map_valid = false;
 }
 
 void release_cache(feasm_pattern* p) {
     if (p->cache) {
-        if (p->cache->base) (void)hipFree(p->cache->base);
+        dev_free(p->alloc, p->cache->base, nullptr);
         delete p->cache;
         p->cache = nullptr;
     }
@@ -488,11 +488,9 @@ extern "C" int reassemble_values(feasm_pattern* p, int fmt, const double* ke, do
     if (strategy == FEASM_SCATTER_OWNER || strategy == FEASM_SCATTER_AUTO) {
         if (!p->owner_map_valid) {
             if (!p->owner_map) {
-                const size_t bytes = sizeof(int32_t) * (size_t)p->n_elem * p->k * p->k;
-                if (hipMalloc((void**)&p->owner_map, bytes) != hipSuccess) {
-                    p->owner_map = nullptr;
-                    FEASM_FAIL(FEASM_ENOMEM, "reassemble_values: cannot allocate lookup record");
-                }
+                const int rc = dev_alloc_n(p->alloc, &p->owner_map, p->n_elem * p->k * p->k, stream,
+                                           "reassemble_values (lookup record)");
+                if (rc != FEASM_OK) return rc;
             }
             const int rc = build_owner_map(p, fmt, stream);
             if (rc != FEASM_OK) return rc;
@@ -506,13 +504,20 @@ extern "C" int reassemble_values(feasm_pattern* p, int fmt, const double* ke, do
     if (p->cache && p->cache->valid && p->cache->fmt == fmt)
         return assemble_impl(p, fmt, ke, values, scatter, p->cache->base, nullptr, stream,
                              "reassemble_values");
-    release_cache(p);
+    if (p->cache) {
+        // queued calls may still read the old cache
+        FEASM_HIP(hipDeviceSynchronize());
+        release_cache(p);
+    }
     p->cache = new (std::nothrow) OffsetCache();
     if (!p->cache) FEASM_FAIL(FEASM_ENOMEM, "reassemble_values: out of host memory");
-    const size_t bytes = sizeof(int32_t) * (size_t)p->n_elem * p->k * p->k;
-    if (hipMalloc((void**)&p->cache->base, bytes) != hipSuccess) {
-        release_cache(p);
-        FEASM_FAIL(FEASM_ENOMEM, "reassemble_values: cannot allocate lookup cache");
+    {
+        const int rc = dev_alloc_n(p->alloc, &p->cache->base, p->n_elem * p->k * p->k, stream,
+                                   "reassemble_values (lookup cache)");
+        if (rc != FEASM_OK) {
+            release_cache(p);
+            return rc;
+        }
     }
     p->cache->fmt = fmt;
     const int rc = assemble_impl(p, fmt, ke, values, scatter, nullptr, p->cache->base, stream,

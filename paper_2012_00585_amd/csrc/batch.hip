@@ -168,6 +168,7 @@ struct Launch {
 }  // namespace feasm
 
 struct feasm_batch {
+    feasm::Allocator alloc;  // every device array of the batch comes from it
     int fmt = 0;
     int64_t count = 0;
     int device = 0;
@@ -361,12 +362,9 @@ void release_batch(feasm_batch* b) {
         if (b->events[i]) (void)hipEventDestroy(b->events[i]);
     }
     void* arrs[] = {b->d_meshes, b->d_counters, b->d_zero, b->d_ke, b->d_values};
-    for (void* a : arrs)
-        if (a) (void)hipFree(a);
-    for (auto& L : b->launches)
-        if (L.d_tiles) (void)hipFree(L.d_tiles);
-    for (auto* c : b->d_colour_ptrs)
-        if (c) (void)hipFree(c);
+    for (void* a : arrs) dev_free(b->alloc, a, nullptr);
+    for (auto& L : b->launches) dev_free(b->alloc, L.d_tiles, nullptr);
+    for (auto* c : b->d_colour_ptrs) dev_free(b->alloc, c, nullptr);
 }
 
 int create(feasm_batch* b, const feasm_pattern* const* patterns, int64_t count, int fmt,
@@ -375,6 +373,7 @@ int create(feasm_batch* b, const feasm_pattern* const* patterns, int64_t count, 
     b->count = count;
     b->accumulate = accumulate;
     (void)hipGetDevice(&b->device);
+    b->alloc = current_allocator();
     b->patterns.assign(patterns, patterns + count);
     b->paths.assign(count, 0);
     if (b->per_mesh_graph) {
@@ -461,7 +460,10 @@ int create(feasm_batch* b, const feasm_pattern* const* patterns, int64_t count, 
         if (strategy == FEASM_SCATTER_COLOURED) {
             A.elem_list = p->colour_elems;
             const int32_t nc = p->n_colours;
-            FEASM_HIP(hipMalloc((void**)&b->d_colour_ptrs[m], sizeof(int64_t) * (nc + 1)));
+            {
+            const int rc__ = dev_alloc(b->alloc, (void**)&b->d_colour_ptrs[m], sizeof(int64_t) * (nc + 1), nullptr, "batch_create");
+            if (rc__ != FEASM_OK) return rc__;
+        }
             FEASM_HIP(hipMemcpy(b->d_colour_ptrs[m], p->colour_ptr.data(),
                                 sizeof(int64_t) * (nc + 1), hipMemcpyHostToDevice));
             D.colour_ptr = b->d_colour_ptrs[m];
@@ -481,7 +483,10 @@ int create(feasm_batch* b, const feasm_pattern* const* patterns, int64_t count, 
             ldsv[0][D.path] = std::max(ldsv[0][D.path], lds);
         }
     }
-    FEASM_HIP(hipMalloc((void**)&b->d_meshes, sizeof(MeshDesc) * count));
+    {
+            const int rc__ = dev_alloc(b->alloc, (void**)&b->d_meshes, sizeof(MeshDesc) * count, nullptr, "batch_create");
+            if (rc__ != FEASM_OK) return rc__;
+        }
     FEASM_HIP(hipMemcpy(b->d_meshes, descs.data(), sizeof(MeshDesc) * count, hipMemcpyHostToDevice));
     int cus = 0;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
@@ -505,7 +510,10 @@ int create(feasm_batch* b, const feasm_pattern* const* patterns, int64_t count, 
             const int64_t cap = (int64_t)cus * std::max(per_cu, 1);
             L.chunk = std::max<int64_t>(1, std::min<int64_t>(32, L.n_tiles / (cap * 8)));
             L.grid = std::max<int64_t>(1, std::min<int64_t>(cap, ceil_div(L.n_tiles, L.chunk)));
-            FEASM_HIP(hipMalloc((void**)&L.d_tiles, sizeof(BatchTile) * tl.size()));
+            {
+            const int rc__ = dev_alloc(b->alloc, (void**)&L.d_tiles, sizeof(BatchTile) * tl.size(), nullptr, "batch_create");
+            if (rc__ != FEASM_OK) return rc__;
+        }
             FEASM_HIP(hipMemcpy(L.d_tiles, tl.data(), sizeof(BatchTile) * tl.size(),
                                 hipMemcpyHostToDevice));
             here.push_back(L);
@@ -514,18 +522,30 @@ int create(feasm_batch* b, const feasm_pattern* const* patterns, int64_t count, 
                          [](const Launch& x, const Launch& y) { return x.work > y.work; });
         b->launches.insert(b->launches.end(), here.begin(), here.end());
     }
-    FEASM_HIP(hipMalloc((void**)&b->d_counters,
-                        sizeof(unsigned long long) * std::max<size_t>(b->launches.size(), 1)));
+    {
+        const int rc = dev_alloc_n(b->alloc, &b->d_counters, (int64_t)b->launches.size(), nullptr,
+                                   "batch_create");
+        if (rc != FEASM_OK) return rc;
+    }
     if ((int64_t)b->launches.size() > 64)
         FEASM_FAIL(FEASM_ELIMIT, "batch_create: more than 64 (phase, path) launches");
     b->n_zero = (int64_t)zero.size();
     if (!zero.empty()) {
-        FEASM_HIP(hipMalloc((void**)&b->d_zero, sizeof(ZeroChunk) * zero.size()));
+        {
+            const int rc__ = dev_alloc(b->alloc, (void**)&b->d_zero, sizeof(ZeroChunk) * zero.size(), nullptr, "batch_create");
+            if (rc__ != FEASM_OK) return rc__;
+        }
         FEASM_HIP(hipMemcpy(b->d_zero, zero.data(), sizeof(ZeroChunk) * zero.size(),
                             hipMemcpyHostToDevice));
     }
-    FEASM_HIP(hipMalloc((void**)&b->d_ke, sizeof(double*) * count));
-    FEASM_HIP(hipMalloc((void**)&b->d_values, sizeof(double*) * count));
+    {
+            const int rc__ = dev_alloc(b->alloc, (void**)&b->d_ke, sizeof(double*) * count, nullptr, "batch_create");
+            if (rc__ != FEASM_OK) return rc__;
+        }
+    {
+            const int rc__ = dev_alloc(b->alloc, (void**)&b->d_values, sizeof(double*) * count, nullptr, "batch_create");
+            if (rc__ != FEASM_OK) return rc__;
+        }
     FEASM_HIP(hipMemset(b->d_ke, 0, sizeof(double*) * count));
     FEASM_HIP(hipMemset(b->d_values, 0, sizeof(double*) * count));
     b->h_ke.assign(count, nullptr);

@@ -135,18 +135,19 @@ unsigned grid(int64_t n, int block) {
 }
 
 struct Buf {
+    Allocator a;
     hipStream_t s;
     std::vector<void*> ptrs;
-    explicit Buf(hipStream_t st) : s(st) {}
+    Buf(const Allocator& al, hipStream_t st) : a(al), s(st) {}
     ~Buf() {
         (void)hipStreamSynchronize(s);
-        for (void* q : ptrs) (void)hipFree(q);
+        for (void* q : ptrs) dev_free(a, q, s);
     }
     template <typename T>
     int alloc(T** p, int64_t n) {
-        FEASM_HIP(hipMalloc((void**)p, sizeof(T) * (size_t)(n > 0 ? n : 1)));
-        ptrs.push_back(*p);
-        return FEASM_OK;
+        const int rc = dev_alloc_n(a, p, n, s, "pattern_build (colouring)");
+        if (rc == FEASM_OK) ptrs.push_back(*p);
+        return rc;
     }
 };
 
@@ -154,11 +155,13 @@ struct Buf {
 
 int build_colouring(feasm_pattern* p, hipStream_t s) {
     const int64_t E = p->n_elem;
-    Buf tmp(s);
+    Buf tmp(p->alloc, s);
     int32_t *stamp, *counters;
-    FEASM_HIP(hipMalloc((void**)&p->elem_colour, sizeof(int32_t) * E));
-    FEASM_HIP(hipMalloc((void**)&p->colour_elems, sizeof(int32_t) * E));
-    if (tmp.alloc(&stamp, E) || tmp.alloc(&counters, 2)) return FEASM_ENOMEM;
+    int rc = dev_alloc_n(p->alloc, &p->elem_colour, E, s, "pattern_build (colouring)");
+    if (rc == FEASM_OK) rc = dev_alloc_n(p->alloc, &p->colour_elems, E, s, "pattern_build (colouring)");
+    if (rc == FEASM_OK) rc = tmp.alloc(&stamp, E);
+    if (rc == FEASM_OK) rc = tmp.alloc(&counters, 2);
+    if (rc != FEASM_OK) return rc;
     k_fill_i32<<<grid(E, 256), 256, 0, s>>>(stamp, E, kUncoloured);
     k_fill_i32<<<grid(E, 256), 256, 0, s>>>(p->elem_colour, E, -1);
     k_fill_i32<<<1, 64, 0, s>>>(counters, 2, 0);
@@ -189,14 +192,16 @@ int build_colouring(feasm_pattern* p, hipStream_t s) {
     const int64_t nc = p->n_colours;
     int32_t* counts;
     int64_t *offs, *scratch, *cptr;
-    if (tmp.alloc(&counts, nc * n_waves) || tmp.alloc(&offs, nc * n_waves + 1) ||
-        tmp.alloc(&scratch, scan_scratch_elems(nc * n_waves)) || tmp.alloc(&cptr, nc + 1))
-        return FEASM_ENOMEM;
+    rc = tmp.alloc(&counts, nc * n_waves);
+    if (rc == FEASM_OK) rc = tmp.alloc(&offs, nc * n_waves + 1);
+    if (rc == FEASM_OK) rc = tmp.alloc(&scratch, scan_scratch_elems(nc * n_waves));
+    if (rc == FEASM_OK) rc = tmp.alloc(&cptr, nc + 1);
+    if (rc != FEASM_OK) return rc;
     k_fill_i32<<<grid(nc * n_waves, 256), 256, 0, s>>>(counts, nc * n_waves, 0);
     const unsigned gb = (unsigned)ceil_div(n_waves * 64, 256);
     k_group<false><<<gb, 256, 0, s>>>(p->elem_colour, E, n_waves, counts, nullptr, nullptr);
     FEASM_HIP(hipGetLastError());
-    int rc = exclusive_scan<int32_t>(counts, nc * n_waves, offs, scratch, s);
+    rc = exclusive_scan<int32_t>(counts, nc * n_waves, offs, scratch, s);
     if (rc != FEASM_OK) return rc;
     k_group<true><<<gb, 256, 0, s>>>(p->elem_colour, E, n_waves, nullptr, offs, p->colour_elems);
     k_gather_ptr<<<(unsigned)ceil_div(nc + 1, 64), 64, 0, s>>>(offs, n_waves, (int32_t)nc, cptr);

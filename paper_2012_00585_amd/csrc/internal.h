@@ -34,6 +34,28 @@ struct Status {
         }                                                                             \
     } while (0)
 
+// ---------------------------------------------------------------- memory
+// The allocator of set_allocator (alloc == nullptr: hipMalloc / hipFree).
+struct Allocator {
+    feasm_alloc_fn alloc = nullptr;
+    feasm_release_fn release = nullptr;
+    void* ctx = nullptr;
+};
+// The allocator set now (objects keep the one they were created with).
+Allocator current_allocator();
+// bytes (0 is allowed and allocates a minimal block) of device memory from
+// `a`; on failure sets the error message (naming `who`) and returns
+// FEASM_ENOMEM or FEASM_EHIP with *ptr = nullptr.
+int dev_alloc(const Allocator& a, void** ptr, size_t bytes, hipStream_t s, const char* who);
+template <typename T>
+int dev_alloc_n(const Allocator& a, T** ptr, int64_t count, hipStream_t s, const char* who) {
+    return dev_alloc(a, reinterpret_cast<void**>(ptr), sizeof(T) * (size_t)(count > 0 ? count : 1), s,
+                     who);
+}
+// Gives ptr (may be null) back to `a`; the caller has made sure that no
+// queued work still uses it.
+void dev_free(const Allocator& a, void* ptr, hipStream_t s);
+
 // ---------------------------------------------------------------- handle
 struct OffsetCache;  // value-only re-assembly lookup cache (assemble.hip)
 
@@ -46,6 +68,7 @@ constexpr int kLightInc = 8;
 
 struct feasm_pattern {
     int device = 0;
+    feasm::Allocator alloc;  // every device array of the handle comes from it
     int64_t n_elem = 0;
     int32_t k = 0, d = 0, n = 0;
     int64_t n_nodes = 0, n_rows = 0;

@@ -51,13 +51,16 @@ int build_node_order(feasm_pattern* p, hipStream_t s, int64_t* n_light_host) {
         set_error(std::string("build_node_order: ") + hipGetErrorString(e));
         rc = e == hipErrorOutOfMemory ? FEASM_ENOMEM : FEASM_EHIP;
     };
-    hipError_t e = hipMalloc((void**)&keys, sizeof(uint64_t) * nn);
-    if (e == hipSuccess) e = hipMalloc((void**)&sorted, sizeof(uint64_t) * nn);
-    if (e == hipSuccess) e = hipMalloc((void**)&d_light, sizeof(int64_t));
-    if (e == hipSuccess) e = hipMalloc((void**)&p->node_order, sizeof(int32_t) * nn);
-    if (e == hipSuccess)
+    const char* who = "pattern_build (node order)";
+    rc = dev_alloc_n(p->alloc, &keys, nn, s, who);
+    if (rc == FEASM_OK) rc = dev_alloc_n(p->alloc, &sorted, nn, s, who);
+    if (rc == FEASM_OK) rc = dev_alloc_n(p->alloc, &d_light, 1, s, who);
+    if (rc == FEASM_OK) rc = dev_alloc_n(p->alloc, &p->node_order, nn, s, who);
+    hipError_t e = hipSuccess;
+    if (rc == FEASM_OK)
         e = hipcub::DeviceRadixSort::SortKeys(nullptr, temp_bytes, keys, sorted, (int)nn, 0, 63, s);
-    if (e == hipSuccess) e = hipMalloc(&temp, std::max<size_t>(temp_bytes, 1));
+    if (rc == FEASM_OK && e == hipSuccess) rc = dev_alloc(p->alloc, &temp, temp_bytes, s, who);
+    if (rc != FEASM_OK) e = hipErrorOutOfMemory;
     const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(nn, 256), 65536);
     if (e == hipSuccess) {
         *n_light_host = nn;
@@ -76,9 +79,9 @@ int build_node_order(feasm_pattern* p, hipStream_t s, int64_t* n_light_host) {
     if (e == hipSuccess)
         e = hipMemcpyAsync(n_light_host, d_light, sizeof(int64_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) fail(e);
-    for (void* q : {(void*)keys, (void*)sorted, (void*)d_light, temp})
-        if (q) (void)hipFree(q);
+    if (e != hipSuccess && rc == FEASM_OK) fail(e);
+    if (e != hipSuccess) (void)hipStreamSynchronize(s);
+    for (void* q : {(void*)keys, (void*)sorted, (void*)d_light, temp}) dev_free(p->alloc, q, s);
     return rc;
 }
 

@@ -296,26 +296,20 @@ unsigned grid_for(int64_t n, int block, int64_t cap = 65536) {
     return (unsigned)(g < cap ? g : cap);
 }
 
-template <typename T>
-int dalloc(T** p, int64_t count) {
-    *p = nullptr;
-    if (count <= 0) count = 1;
-    FEASM_HIP(hipMalloc((void**)p, sizeof(T) * (size_t)count));
-    return FEASM_OK;
-}
-
-// Temporary device buffers, released after the stream has drained.
+// Temporary device buffers of one build, released after the stream has
+// drained.
 struct TempFree {
+    Allocator a;
     hipStream_t s;
     std::vector<void*> ptrs;
-    explicit TempFree(hipStream_t st) : s(st) {}
+    TempFree(const Allocator& al, hipStream_t st) : a(al), s(st) {}
     ~TempFree() {
         (void)hipStreamSynchronize(s);
-        for (void* q : ptrs) (void)hipFree(q);
+        for (void* q : ptrs) dev_free(a, q, s);
     }
     template <typename T>
     int alloc(T** p, int64_t count) {
-        int rc = dalloc(p, count);
+        int rc = dev_alloc_n(a, p, count, s, "pattern_build");
         if (rc == FEASM_OK) ptrs.push_back(*p);
         return rc;
     }
@@ -330,9 +324,9 @@ struct TempFree {
 int build(feasm_pattern* p, const int32_t* conn_in, hipStream_t s) {
     const int64_t E = p->n_elem, k = p->k, d = p->d, nn = p->n_nodes;
     const int64_t ek = E * k;
-    TempFree tmp(s);
+    TempFree tmp(p->alloc, s);
 
-    TRY(dalloc(&p->conn, ek));
+    TRY(dev_alloc_n(p->alloc, &p->conn, ek, s, "pattern_build"));
     FEASM_HIP(hipMemcpyAsync(p->conn, conn_in, sizeof(int32_t) * ek, hipMemcpyDeviceToDevice, s));
 
     BuildStatus* st;
@@ -361,10 +355,10 @@ int build(feasm_pattern* p, const int32_t* conn_in, hipStream_t s) {
     int64_t* scratch;
     const int64_t scratch_n = scan_scratch_elems(nn + 1);
     TRY(tmp.alloc(&scratch, scratch_n));
-    TRY(dalloc(&p->inc_ptr, nn + 1));
+    TRY(dev_alloc_n(p->alloc, &p->inc_ptr, nn + 1, s, "pattern_build"));
     // padded so that a row's incidence entries can be read in whole
     // batches of up to kIncPad entries with scalar loads
-    TRY(dalloc(&p->inc_q, ek + kIncPad));
+    TRY(dev_alloc_n(p->alloc, &p->inc_q, ek + kIncPad, s, "pattern_build"));
     FEASM_HIP(hipMemsetAsync(p->inc_q + ek, 0, sizeof(int32_t) * kIncPad, s));
     TRY(exclusive_scan<int32_t>(inc_count, nn, p->inc_ptr, scratch, s));
     k_fill_incidence<<<grid_for(ek, 256), 256, 0, s>>>(p->conn, ek, p->inc_ptr, cursor, p->inc_q);
@@ -373,7 +367,7 @@ int build(feasm_pattern* p, const int32_t* conn_in, hipStream_t s) {
     // 2. per-node degree and run count
     int32_t *deg, *big_list;
     TRY(tmp.alloc(&deg, nn));
-    TRY(dalloc(&p->node_nruns, nn));
+    TRY(dev_alloc_n(p->alloc, &p->node_nruns, nn, s, "pattern_build"));
     TRY(tmp.alloc(&big_list, nn));
     k_node_rows<kSmallBlock, kSmallCap, false><<<grid_for(nn, 1, 1 << 20), kSmallBlock, 0, s>>>(
         p->conn, (int32_t)k, p->inc_ptr, p->inc_q, nn, nullptr, nullptr, deg, p->node_nruns,
@@ -385,8 +379,8 @@ int build(feasm_pattern* p, const int32_t* conn_in, hipStream_t s) {
     FEASM_HIP(hipGetLastError());
 
     // 3. offsets; the single read-back of sizes
-    TRY(dalloc(&p->node_ptr, nn + 1));
-    TRY(dalloc(&p->noderun_ptr, nn + 1));
+    TRY(dev_alloc_n(p->alloc, &p->node_ptr, nn + 1, s, "pattern_build"));
+    TRY(dev_alloc_n(p->alloc, &p->noderun_ptr, nn + 1, s, "pattern_build"));
     TRY(exclusive_scan<int32_t>(deg, nn, p->node_ptr, scratch, s));
     TRY(exclusive_scan<int32_t>(p->node_nruns, nn, p->noderun_ptr, scratch, s));
     int64_t totals[2];
@@ -411,7 +405,7 @@ int build(feasm_pattern* p, const int32_t* conn_in, hipStream_t s) {
                                         " does not fit int32");
 
     // 4. neighbour lists
-    TRY(dalloc(&p->node_col, p->node_nnz));
+    TRY(dev_alloc_n(p->alloc, &p->node_col, p->node_nnz, s, "pattern_build"));
     k_node_rows<kSmallBlock, kSmallCap, true><<<grid_for(nn, 1, 1 << 20), kSmallBlock, 0, s>>>(
         p->conn, (int32_t)k, p->inc_ptr, p->inc_q, nn, nullptr, nullptr, nullptr, nullptr,
         p->node_ptr, p->node_col, nullptr, st);
@@ -424,8 +418,8 @@ int build(feasm_pattern* p, const int32_t* conn_in, hipStream_t s) {
         (int32_t)k, p->inc_ptr, p->inc_q, nn, nullptr, nullptr);
     k_sort_incidence<kBigBlock, kBigCap><<<256, kBigBlock, 0, s>>>(
         (int32_t)k, p->inc_ptr, p->inc_q, nn, big_list, &st->big_count);
-    TRY(dalloc(&p->inc_local, ek));
-    TRY(dalloc(&p->inc_elem, ek));
+    TRY(dev_alloc_n(p->alloc, &p->inc_local, ek, s, "pattern_build"));
+    TRY(dev_alloc_n(p->alloc, &p->inc_elem, ek, s, "pattern_build"));
     k_split_incidence<<<grid_for(ek, 256), 256, 0, s>>>(ek, (int32_t)k, p->inc_q, p->inc_elem,
                                                         p->inc_local);
     FEASM_HIP(hipGetLastError());
@@ -433,14 +427,14 @@ int build(feasm_pattern* p, const int32_t* conn_in, hipStream_t s) {
     // 5. DOF-level arrays
     const bool want_csr = p->flags & FEASM_BUILD_CSR;
     const bool want_crac = p->flags & FEASM_BUILD_CRAC;
-    TRY(dalloc(&p->row_ptr, p->n_rows + 1));
-    if (want_csr) TRY(dalloc(&p->col_idx, p->nnz));
+    TRY(dev_alloc_n(p->alloc, &p->row_ptr, p->n_rows + 1, s, "pattern_build"));
+    if (want_csr) TRY(dev_alloc_n(p->alloc, &p->col_idx, p->nnz, s, "pattern_build"));
     k_expand_csr<<<grid_for(nn, 1, 1 << 20), 64, 0, s>>>(nn, (int32_t)d, p->node_ptr, p->node_col,
                                                          p->row_ptr, p->col_idx);
     FEASM_HIP(hipGetLastError());
     if (want_crac) {
-        TRY(dalloc(&p->crac_row_ptr, p->n_rows + 1));
-        TRY(dalloc(&p->ca, p->n_ca));
+        TRY(dev_alloc_n(p->alloc, &p->crac_row_ptr, p->n_rows + 1, s, "pattern_build"));
+        TRY(dev_alloc_n(p->alloc, &p->ca, p->n_ca, s, "pattern_build"));
         k_build_crac<<<grid_for(nn, 1, 1 << 20), 64, 0, s>>>(
             nn, (int32_t)d, p->node_ptr, p->node_col, p->node_nruns, p->noderun_ptr,
             p->crac_row_ptr, p->ca);
@@ -466,8 +460,7 @@ void release_pattern(feasm_pattern* p) {
                     p->inc_ptr, p->inc_q,        p->inc_elem, p->inc_local,
                     p->row_ptr,  p->col_idx,    p->crac_row_ptr,
                     p->ca,      p->colour_elems, p->elem_colour, p->node_order};
-    for (void* a : arrs)
-        if (a) (void)hipFree(a);
+    for (void* a : arrs) dev_free(p->alloc, a, nullptr);
     release_cache(p);
     release_owner_map(p);
 }
@@ -498,6 +491,7 @@ extern "C" int pattern_build(const int32_t* conn, int64_t n_elem, int32_t nodes_
     feasm_pattern* p = new (std::nothrow) feasm_pattern();
     if (!p) FEASM_FAIL(FEASM_ENOMEM, "pattern_build: out of host memory");
     (void)hipGetDevice(&p->device);
+    p->alloc = current_allocator();
     p->n_elem = n_elem;
     p->k = nodes_per_elem;
     p->d = dofs_per_node;

@@ -76,12 +76,12 @@ extern "C" int serve_run(const feasm_pattern* const* meshes, const int32_t* reci
     (void)total_re;
 
     std::vector<Slot> slots(n_slots);
+    const Allocator alloc = current_allocator();
     auto cleanup = [&]() {
         for (Slot& s : slots) {
             if (s.main) (void)hipStreamSynchronize(s.main);
             if (s.side) (void)hipStreamSynchronize(s.side);
-            for (double* q : {s.ke[0], s.ke[1], s.values})
-                if (q) (void)hipFree(q);
+            for (double* q : {s.ke[0], s.ke[1], s.values}) dev_free(alloc, q, nullptr);
             for (hipEvent_t e : {s.done, s.gen[0], s.gen[1]})
                 if (e) (void)hipEventDestroy(e);
             if (s.main) (void)hipStreamDestroy(s.main);
@@ -98,9 +98,11 @@ extern "C" int serve_run(const feasm_pattern* const* meshes, const int32_t* reci
         FEASM_HIP(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
         for (int b = 0; b < 2; ++b) {
             FEASM_HIP(hipEventCreateWithFlags(&s.gen[b], hipEventDisableTiming));
-            FEASM_HIP(hipMalloc((void**)&s.ke[b], sizeof(double) * (size_t)std::max<int64_t>(max_ke, 1)));
+            const int rc = dev_alloc_n(alloc, &s.ke[b], max_ke, nullptr, "serve_run");
+            if (rc != FEASM_OK) return rc;
         }
-        FEASM_HIP(hipMalloc((void**)&s.values, sizeof(double) * (size_t)std::max<int64_t>(max_nnz, 1)));
+        const int rc = dev_alloc_n(alloc, &s.values, max_nnz, nullptr, "serve_run");
+        if (rc != FEASM_OK) return rc;
     }
     // offsets of each request's re-assembly latencies in the flat output
     std::vector<int64_t> re_off(n_requests + 1, 0);

@@ -13,6 +13,7 @@ HEADER = os.path.join(ROOT, "include", "feasm.h")
 def _declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"^\s*typedef[^;]*;", "", text, flags=re.M)
     names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(\w+)\s*\(", text, flags=re.M)
     return sorted(set(n for n in names if n not in ("if", "defined")))
 
@@ -37,6 +38,19 @@ def test_every_declared_symbol_is_exported(lib):
     assert set(names) == set(_lib.SIGNATURES), (names, sorted(_lib.SIGNATURES))
     for n in names:
         assert hasattr(lib, n), n
+
+
+def test_set_allocator_needs_both_callbacks(lib):
+    """Host-only: one callback without the other is rejected; none restores
+    the default."""
+    from paper_2012_00585_amd import _lib
+
+    alloc = _lib.ALLOC_FN(lambda nbytes, stream, ctx: None)
+    release = _lib.RELEASE_FN(lambda ptr, stream, ctx: None)
+    assert lib.set_allocator(alloc, _lib.RELEASE_FN(), None) == -1
+    assert b"both" in lib.last_error()
+    assert lib.set_allocator(_lib.ALLOC_FN(), release, None) == -1
+    assert lib.set_allocator(_lib.ALLOC_FN(), _lib.RELEASE_FN(), None) == 0
 
 
 def _build(lib, conn, E, k, d, nn, flags):
