@@ -244,6 +244,11 @@ def main():
             # the element matrices alone: the stream every strategy must read
             "Ke_only_GBps": w.n_elem * w.n * w.n * 8 / (t_sc["mean"] * 1e-3) / 1e9,
         }
+        if strategy == "atomic":
+            # one FP64 atomic add per element-matrix entry (the second ceiling
+            # of this method besides HBM bandwidth)
+            variants[name]["atomic_adds_per_launch"] = w.n_elem * w.n * w.n
+            variants[name]["atomic_adds_per_s"] = w.n_elem * w.n * w.n / (t_sc["mean"] * 1e-3)
     log("[bench] value-only re-assembly latency")
     reasm = {}
     for name, fmt, sc in (("csr_atomic", feasm.FMT_CSR, A), ("crac_atomic", feasm.FMT_CRAC, A),
