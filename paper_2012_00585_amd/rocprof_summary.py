@@ -67,7 +67,7 @@ def kernel_durations(db):
     """{kernel name: [durations in us]} from a kernel-trace database."""
     c = sqlite3.connect(db)
     out = collections.defaultdict(list)
-    for name, start, end in c.execute("select name, start, end from kernels"):
+    for name, start, end in c.execute("select name, start, end from kernels order by start"):
         out[name].append((end - start) / 1e3)
     return dict(out)
 
@@ -113,11 +113,16 @@ def summarize(trace, fetch, write, kernel, copy_mib, workload, command, algorith
     for c in command:
         lines.append(f"    {c}")
     lines.append("")
-    lines.append("| kernel | dispatches | mean us | min us |")
-    lines.append("|---|---|---|---|")
+    # "warm" leaves out each kernel's first dispatch, which also pays for
+    # first-touch page mapping of its buffers
+    lines.append("| kernel | dispatches | mean us | warm mean us | median us | min us |")
+    lines.append("|---|---|---|---|---|---|")
     for nme in sorted(names, key=lambda x: -len(durs[x])):
         v = durs[nme]
-        lines.append(f"| {nme[:100]} | {len(v)} | {sum(v) / len(v):.2f} | {min(v):.2f} |")
+        warm = v[1:] if len(v) > 1 else v
+        med = sorted(v)[len(v) // 2]
+        lines.append(f"| {nme[:100]} | {len(v)} | {sum(v) / len(v):.2f} | "
+                     f"{sum(warm) / len(warm):.2f} | {med:.2f} | {min(v):.2f} |")
     lines.append("")
     copies = [d for k in _match(durs, r"copyBuffer|copy") for d in durs[k]]
     if copies and copy_mib:
