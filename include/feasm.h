@@ -339,7 +339,7 @@ enum { FEASM_BATCH_PER_MESH_GRAPH = 0x200 };
  * symmetric positive definite B B^T / n + I with unit-variance B.  Element
  * e uses counter ((entry), e + elem_offset, recipe) under key `seed`, with
  * exact or correctly rounded operations only, so any implementation of the
- * same definition reproduces the bits.  Asynchronous; n*n*8 <= 64 KiB.
+ * same definition reproduces the bits.  Asynchronous; n*(n+1)*8 <= 64 KiB.
  */
 int generate_ke(int recipe, int64_t n_elem, int32_t n, uint64_t seed, int64_t elem_offset,
                 double* ke, hipStream_t stream);
@@ -390,7 +390,8 @@ int set_allocator(feasm_alloc_fn alloc, feasm_release_fn release, void* ctx);
  * every slot issues its next iteration as soon as the previous completes,
  * so admitted requests overlap on the device.  Runs until every request is
  * done; times are host seconds since the call started.  Slot buffers are
- * allocated once, for the largest mesh.  Synchronous; uses AUTO strategy.
+ * allocated once, for the largest mesh, and each mesh's re-assembly lookup
+ * state is built before the clock starts.  Synchronous; uses AUTO strategy.
  *   meshes/recipes  host arrays [n_meshes]: handles, generate_ke recipes
  *   requests        host array [n_requests], sorted by arrival_s
  *   results         host array [n_requests]

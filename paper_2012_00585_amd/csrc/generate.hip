@@ -43,14 +43,19 @@ __device__ inline void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2, u
 constexpr double kTwoM32 = 2.3283064365386963e-10;  // 2^-32
 constexpr double kSqrt12 = 3.4641016151377544;
 
-// One 64-lane block per element; the uniforms in LDS, the product in 4x4
-// register blocks (upper triangle of blocks, mirrored).
+// One 64-lane block per element; the uniforms in LDS (recipe 1: rows
+// padded by one value, so that lanes reading different rows hit different
+// banks), then the matrix.  Recipe 1 computes every entry, both triangles,
+// in 3x3 register blocks: K_sr sums the same products (B_st B_rt equals
+// B_rt B_st exactly) in the same order as K_rs, so the matrix is exactly
+// symmetric, and all 64 lanes have work (8 x 8 blocks for n = 24).
 __global__ void __launch_bounds__(64)
     k_gen(int recipe, int64_t n_elem, int32_t n, uint32_t k0, uint32_t k1, int64_t e0,
           double* __restrict__ ke) {
-    extern __shared__ double B[];  // [n*n]
+    extern __shared__ double B[];  // [n][ldb]
     const int32_t n2 = n * n;
-    const int32_t nb = (n + 3) >> 2;
+    const int32_t ldb = recipe == 0 ? n : n + 1;
+    const int32_t nb = (n + 2) / 3;
     for (int64_t e = blockIdx.x; e < n_elem; e += gridDim.x) {
         const uint64_t ge = (uint64_t)(e + e0);
         double* K = ke + e * (int64_t)n2;
@@ -62,7 +67,8 @@ __global__ void __launch_bounds__(64)
                 const int32_t i = c * 4 + q;
                 if (i < n2) {
                     const double u = (double)w[q] * kTwoM32;
-                    B[i] = recipe == 0 ? 2.0 * u - 1.0 : (u - 0.5) * kSqrt12;
+                    const int32_t r = i / n, s = i - r * n;
+                    B[r * ldb + s] = recipe == 0 ? 2.0 * u - 1.0 : (u - 0.5) * kSqrt12;
                 }
             }
         }
@@ -83,31 +89,29 @@ __global__ void __launch_bounds__(64)
             const double dn = (double)n;
             for (int32_t bi = threadIdx.x; bi < nb * nb; bi += 64) {
                 const int32_t R = bi / nb, S = bi - R * nb;
-                if (S < R) continue;
-                double acc[4][4] = {};
+                double acc[3][3] = {};
                 for (int32_t t = 0; t < n; ++t) {
-                    double br[4], bs[4];
+                    double br[3], bs[3];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int32_t r = 4 * R + q, s = 4 * S + q;
-                        br[q] = r < n ? B[r * n + t] : 0.0;
-                        bs[q] = s < n ? B[s * n + t] : 0.0;
+                    for (int q = 0; q < 3; ++q) {
+                        const int32_t r = 3 * R + q, s = 3 * S + q;
+                        br[q] = r < n ? B[r * ldb + t] : 0.0;
+                        bs[q] = s < n ? B[s * ldb + t] : 0.0;
                     }
 #pragma unroll
-                    for (int a = 0; a < 4; ++a)
+                    for (int a = 0; a < 3; ++a)
 #pragma unroll
-                        for (int b = 0; b < 4; ++b) acc[a][b] = acc[a][b] + br[a] * bs[b];
+                        for (int b = 0; b < 3; ++b) acc[a][b] = acc[a][b] + br[a] * bs[b];
                 }
 #pragma unroll
-                for (int a = 0; a < 4; ++a)
+                for (int a = 0; a < 3; ++a)
 #pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        const int32_t r = 4 * R + a, s = 4 * S + b;
+                    for (int b = 0; b < 3; ++b) {
+                        const int32_t r = 3 * R + a, s = 3 * S + b;
                         if (r < n && s < n) {
                             double v = acc[a][b] / dn;
                             if (r == s) v = v + 1.0;
                             K[r * n + s] = v;
-                            K[s * n + r] = v;
                         }
                     }
             }
@@ -125,11 +129,12 @@ extern "C" int generate_ke(int recipe, int64_t n_elem, int32_t n, uint64_t seed,
     if (!ke) FEASM_FAIL(FEASM_EINVAL, "generate_ke: ke is NULL");
     if (recipe != 0 && recipe != 1) FEASM_FAIL(FEASM_EINVAL, "generate_ke: unknown recipe");
     if (n_elem < 0 || n <= 0 || elem_offset < 0) FEASM_FAIL(FEASM_EINVAL, "generate_ke: bad size");
-    if ((int64_t)n * n * 8 > 64 * 1024) FEASM_FAIL(FEASM_ELIMIT, "generate_ke: n too large");
+    if ((int64_t)n * (n + 1) * 8 > 64 * 1024) FEASM_FAIL(FEASM_ELIMIT, "generate_ke: n too large");
     if (n_elem == 0) return FEASM_OK;
     const unsigned grid = (unsigned)std::min<int64_t>(n_elem, 1 << 20);
-    k_gen<<<grid, 64, (size_t)n * n * 8, stream>>>(recipe, n_elem, n, (uint32_t)seed,
-                                                   (uint32_t)(seed >> 32), elem_offset, ke);
+    const size_t lds = (size_t)n * (recipe == 0 ? n : n + 1) * 8;
+    k_gen<<<grid, 64, lds, stream>>>(recipe, n_elem, n, (uint32_t)seed, (uint32_t)(seed >> 32),
+                                     elem_offset, ke);
     FEASM_HIP(hipGetLastError());
     return FEASM_OK;
 }
