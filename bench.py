@@ -205,8 +205,8 @@ def main():
             p.free()
     values = torch.zeros(p.nnz, dtype=torch.float64, device=dev)
 
-    A, C, O, ACC = (feasm.SCATTER_ATOMIC, feasm.SCATTER_COLOURED, feasm.SCATTER_OWNER,
-                    feasm.ACCUMULATE)
+    A, C, O, S, ACC = (feasm.SCATTER_ATOMIC, feasm.SCATTER_COLOURED, feasm.SCATTER_OWNER,
+                       feasm.SCATTER_SPIN, feasm.ACCUMULATE)
     full = {
         "csr_owner": lambda: feasm.assemble_csr(p, ke_d, values, O),
         "crac_owner": lambda: feasm.assemble_crac(p, ke_d, values, O),
@@ -214,6 +214,8 @@ def main():
         "crac_atomic": lambda: feasm.assemble_crac(p, ke_d, values, A),
         "csr_coloured": lambda: feasm.assemble_csr(p, ke_d, values, C),
         "crac_coloured": lambda: feasm.assemble_crac(p, ke_d, values, C),
+        "csr_spin": lambda: feasm.assemble_csr(p, ke_d, values, S),
+        "crac_spin": lambda: feasm.assemble_crac(p, ke_d, values, S),
     }
     scatter_only = {
         "csr_owner": lambda: feasm.assemble_csr(p, ke_d, values, O),
@@ -222,6 +224,8 @@ def main():
         "crac_atomic": lambda: feasm.assemble_crac(p, ke_d, values, A | ACC),
         "csr_coloured": lambda: feasm.assemble_csr(p, ke_d, values, C | ACC),
         "crac_coloured": lambda: feasm.assemble_crac(p, ke_d, values, C | ACC),
+        "csr_spin": lambda: feasm.assemble_csr(p, ke_d, values, S | ACC),
+        "crac_spin": lambda: feasm.assemble_crac(p, ke_d, values, S | ACC),
     }
     reps = max(args.steps, 5)
     variants = {}

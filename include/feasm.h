@@ -71,6 +71,15 @@ enum {
     FEASM_SCATTER_OWNER = 3,    /* row-owned: each node row is summed by one wavefront
                                    from the incident elements, in element order, and
                                    written once (no atomics, no reset pass) */
+    FEASM_SCATTER_SPIN = 4,     /* row locks (the spin-lock methods of Section 3.3): one
+                                   lane per element row locks its global row, adds the
+                                   row slice with device-coherent reads and writes, and
+                                   unlocks; element rows of at most 32 entries (ELIMIT
+                                   otherwise).  Each acquire loop is bounded by the spin
+                                   limit (FEASM_TUNE_SPIN_LIMIT, default 2^20 attempts);
+                                   a lane that reaches it leaves its row out and is
+                                   counted by spin_aborts.  Sums in lock order (values
+                                   within rounding of the sequential assembly) */
     FEASM_ACCUMULATE = 0x100    /* or-ed into `scatter`: add into `values` without
                                    resetting it first (values += sum_e scatter(K_e)) */
 };
@@ -218,6 +227,10 @@ int pattern_colouring(const feasm_pattern* p, const int64_t** colour_ptr,
  *                                   n in [1, 16] = the pipelined grid with n
  *                                   blocks per compute unit; -1 = every node
  *                                   one per wavefront
+ *   FEASM_TUNE_SPIN_LIMIT           FEASM_SCATTER_SPIN: lock acquire attempts
+ *                                   per lane before it gives up (0: 2^20;
+ *                                   -1: none, every lane gives up at once,
+ *                                   which exercises the give-up path)
  * Returns EINVAL for an unknown key or value.
  */
 enum {
@@ -229,7 +242,8 @@ enum {
     FEASM_TUNE_OWNER_FLAT = 6,
     FEASM_TUNE_OWNER_PREFETCH = 7,
     FEASM_TUNE_SPMV_CHUNK = 8,
-    FEASM_TUNE_HEX8_PIPE = 9
+    FEASM_TUNE_HEX8_PIPE = 9,
+    FEASM_TUNE_SPIN_LIMIT = 10
 };
 int pattern_tune(feasm_pattern* p, int key, int64_t value);
 
@@ -296,6 +310,14 @@ int hex8_element_matrices(const feasm_pattern* p, const double* coords, const do
                           double* ke, hipStream_t stream);
 int assemble_hex8(const feasm_pattern* p, int fmt, const double* coords, const double* material,
                   double* values, int flags, hipStream_t stream);
+
+/*
+ * Lanes of FEASM_SCATTER_SPIN launches on this handle that reached the spin
+ * limit since the last call (their rows' contributions are missing from
+ * those results); synchronises the device and clears the count.  0 when
+ * the handle never ran that strategy.  EINVAL for a null argument.
+ */
+int spin_aborts(feasm_pattern* p, int64_t* count);
 
 /* Releases the handle and its device arrays (synchronises the device). NULL is ignored. */
 void pattern_free(feasm_pattern* p);

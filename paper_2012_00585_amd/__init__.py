@@ -29,6 +29,7 @@ SCATTER_AUTO = 0
 SCATTER_ATOMIC = 1
 SCATTER_COLOURED = 2
 SCATTER_OWNER = 3
+SCATTER_SPIN = 4
 ACCUMULATE = 0x100  # or into `scatter`: add into values without resetting them
 
 TUNE_OWNER_BLOCKS_PER_CU = 1
@@ -40,6 +41,7 @@ TUNE_OWNER_FLAT = 6
 TUNE_OWNER_PREFETCH = 7
 TUNE_SPMV_CHUNK = 8
 TUNE_HEX8_PIPE = 9
+TUNE_SPIN_LIMIT = 10
 
 _HIP_D2D = 3  # hipMemcpyDeviceToDevice
 
@@ -137,6 +139,12 @@ class Pattern:
     def tune(self, key: int, value: int):
         """Set a launch-shape knob of this handle (0 = library default)."""
         _lib.check(_lib.load().pattern_tune(self.handle, key, value), "pattern_tune")
+
+    def spin_aborts(self) -> int:
+        """Row-lock lanes that gave up since the last call (synchronises)."""
+        c = ctypes.c_int64()
+        _lib.check(_lib.load().spin_aborts(self.handle, ctypes.byref(c)), "spin_aborts")
+        return c.value
 
     def free(self):
         if self._h is not None:

@@ -70,6 +70,7 @@ SIGNATURES = {
                         ctypes.POINTER(RequestResult), P]),
     "last_error": (ctypes.c_char_p, []),
     "set_allocator": (INT, [ALLOC_FN, RELEASE_FN, P]),
+    "spin_aborts": (INT, [P, PI64]),
 }
 
 _lib = None

@@ -380,10 +380,18 @@ int assemble_impl(const feasm_pattern* p, int fmt, const double* ke, double* val
             scatter = owner_fits(p, fmt) ? FEASM_SCATTER_OWNER : FEASM_SCATTER_ATOMIC;
     }
     if (scatter != FEASM_SCATTER_ATOMIC && scatter != FEASM_SCATTER_COLOURED &&
-        scatter != FEASM_SCATTER_OWNER)
+        scatter != FEASM_SCATTER_OWNER && scatter != FEASM_SCATTER_SPIN)
         FEASM_FAIL(FEASM_EINVAL, std::string(who) + ": unknown scatter strategy");
     if (scatter == FEASM_SCATTER_OWNER)
         return launch_owner(p, fmt, ke, values, accumulate, s, owner_map);
+    if (scatter == FEASM_SCATTER_SPIN) {
+        if (!accumulate) {
+            k_zero<<<(unsigned)std::min<int64_t>(ceil_div(p->nnz / 2 + 1, 256), 16384), 256, 0, s>>>(
+                values, p->nnz);
+            FEASM_HIP(hipGetLastError());
+        }
+        return launch_spin(p, fmt, ke, values, s);
+    }
     if (scatter == FEASM_SCATTER_COLOURED && !(p->flags & FEASM_BUILD_COLOUR))
         FEASM_FAIL(FEASM_EINVAL,
                    std::string(who) + ": coloured scatter needs a handle built with colouring");
@@ -485,6 +493,9 @@ extern "C" int reassemble_values(feasm_pattern* p, int fmt, const double* ke, do
             strategy = owner_fits(p, fmt) ? FEASM_SCATTER_OWNER : FEASM_SCATTER_ATOMIC;
         scatter = strategy | (scatter & FEASM_ACCUMULATE);
     }
+    if (strategy == FEASM_SCATTER_SPIN)
+        return assemble_impl(p, fmt, ke, values, scatter, nullptr, nullptr, stream,
+                             "reassemble_values");
     if (strategy == FEASM_SCATTER_OWNER || strategy == FEASM_SCATTER_AUTO) {
         if (!p->owner_map_valid) {
             if (!p->owner_map) {
@@ -564,6 +575,12 @@ extern "C" int pattern_tune(feasm_pattern* p, int key, int64_t value) {
         if (value != 0 && value != 256 && value != 512 && value != 1024 && value != 2048)
             FEASM_FAIL(FEASM_EINVAL, "pattern_tune: spmv chunk must be 256, 512, 1024 or 2048");
         p->tune_spmv_chunk = (int32_t)value;
+        return FEASM_OK;
+    }
+    if (key == FEASM_TUNE_SPIN_LIMIT) {
+        if (value < -1 || value > ((int64_t)1 << 40))
+            FEASM_FAIL(FEASM_EINVAL, "pattern_tune: spin limit must be -1 or in [0, 2^40]");
+        p->tune_spin_limit = value;
         return FEASM_OK;
     }
     if (key == FEASM_TUNE_HEX8_PIPE) {

@@ -115,6 +115,8 @@ struct feasm_pattern {
     int64_t n_light = 0;
     int32_t* owner_map = nullptr;  // dev [n_elem*k][k]: row-owned lookup record
     bool owner_map_valid = false;
+    int32_t* row_locks = nullptr;    // dev [n_rows]: row-lock scatter (zero between launches)
+    int32_t* spin_aborts = nullptr;  // dev [1]: lanes that reached the spin limit
 
     // tuning (0 = library default)
     int32_t tune_owner_blocks_per_cu = 0;  // >0: persistent row-owned grid of this size per CU
@@ -125,6 +127,7 @@ struct feasm_pattern {
     int32_t tune_owner_flat = 0;           // flat batches: -1 off, 0 auto, else entries per batch
     int32_t tune_owner_prefetch = 0;       // flat batches: issue the next batch early
     int32_t tune_spmv_chunk = 0;           // matrix-vector product: values per LDS chunk
+    int64_t tune_spin_limit = 0;           // row-lock scatter: acquire attempts per lane
     int32_t tune_hex8_pipe = 0;            // fused hexahedra: -1 one node per wavefront, 0 auto,
                                            // else pipelined blocks per CU
 };
@@ -145,6 +148,9 @@ int build_node_order(feasm_pattern* p, hipStream_t s, int64_t* n_light_host);
 
 // Colouring (colour.hip): fills p->elem_colour, colour_elems, colour_ptr, n_colours.
 int build_colouring(feasm_pattern* p, hipStream_t s);
+
+// Row-lock scatter (spin.hip) of one mesh into reset (or accumulated) values.
+int launch_spin(const feasm_pattern* p, int fmt, const double* ke, double* values, hipStream_t s);
 
 // The numeric phase of one mesh on a stream (asynchronous; used by batches).
 int assemble_on_stream(const feasm_pattern* p, int fmt, const double* ke, double* values,

@@ -459,7 +459,8 @@ void release_pattern(feasm_pattern* p) {
     void* arrs[] = {p->conn,    p->node_ptr,     p->node_col, p->node_nruns, p->noderun_ptr,
                     p->inc_ptr, p->inc_q,        p->inc_elem, p->inc_local,
                     p->row_ptr,  p->col_idx,    p->crac_row_ptr,
-                    p->ca,      p->colour_elems, p->elem_colour, p->node_order};
+                    p->ca,      p->colour_elems, p->elem_colour, p->node_order,
+                    p->row_locks, p->spin_aborts};
     for (void* a : arrs) dev_free(p->alloc, a, nullptr);
     release_cache(p);
     release_owner_map(p);
