@@ -163,6 +163,10 @@ int launch_owner_f(const feasm_pattern* p, OwnArgs& A, hipStream_t s) {
         ((p->d == 3 && p->n == 24) || (p->d == 3 && p->n == 30))) {
         const size_t lds8 = (size_t)A.group_bytes + (size_t)2 * 8 * p->k * 4;
         const size_t lds16 = (size_t)A.group_bytes + (size_t)2 * 16 * p->k * 4;
+        const size_t lds24 = (size_t)A.group_bytes + (size_t)2 * 24 * p->k * 4;
+        // heavy rows of at most 24 entries (vertex nodes of tet10 meshes)
+        // take one batch of 24, with every load issued at once
+        const bool one24 = p->max_inc <= 24 && lds24 <= 64 * 1024 && !p->tune_owner_prefetch;
         if (lds16 <= 64 * 1024) {
             const int64_t nl = p->n_light, nh = p->n_nodes - p->n_light;
             OwnArgs L = A, H = A;
@@ -172,7 +176,9 @@ int launch_owner_f(const feasm_pattern* p, OwnArgs& A, hipStream_t s) {
     if (p->d == DD && p->n == NN) {                                                    \
         if (nl > 0) k_owner_pipe<FMT, DD, NN, 8, 0><<<(unsigned)nl, 64, lds8, s>>>(L);  \
         if (nh > 0) {                                                                  \
-            if (p->tune_owner_prefetch)                                                \
+            if (one24)                                                                 \
+                k_owner_pipe<FMT, DD, NN, 24, 0><<<(unsigned)nh, 64, lds24, s>>>(H);   \
+            else if (p->tune_owner_prefetch)                                           \
                 k_owner_pipe<FMT, DD, NN, 16, 2><<<(unsigned)nh, 64, lds16, s>>>(H);   \
             else                                                                       \
                 k_owner_pipe<FMT, DD, NN, 16, 1><<<(unsigned)nh, 64, lds16, s>>>(H);   \
