@@ -160,8 +160,9 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(see the sharding design); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(rows would be sharded in contiguous blocks per GPU); use --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
