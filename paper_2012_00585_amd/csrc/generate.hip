@@ -43,25 +43,84 @@ __device__ inline void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2, u
 constexpr double kTwoM32 = 2.3283064365386963e-10;  // 2^-32
 constexpr double kSqrt12 = 3.4641016151377544;
 
+// The four words of entries 4c .. 4c+3 of global element ge.
+__device__ inline void philox_block(int32_t c, uint64_t ge, int recipe, uint32_t k0, uint32_t k1,
+                                    uint32_t (&w)[4]) {
+    w[0] = (uint32_t)c;
+    w[1] = (uint32_t)ge;
+    w[2] = (uint32_t)(ge >> 32);
+    w[3] = (uint32_t)recipe;
+    philox4x32_10(w[0], w[1], w[2], w[3], k0, k1);
+}
+
+// Uniform u of entry i of global element ge (word i mod 4 of its block).
+__device__ inline double entry_uniform(int32_t i, uint64_t ge, int recipe, uint32_t k0, uint32_t k1) {
+    uint32_t w[4];
+    philox_block(i >> 2, ge, recipe, k0, k1, w);
+    const int q = i & 3;
+    const uint32_t word = q == 0 ? w[0] : q == 1 ? w[1] : q == 2 ? w[2] : w[3];
+    return (double)word * kTwoM32;
+}
+
+// Diagonal entry r of the zero-row-sum recipe from its strict upper
+// triangle U (row-major, n columns): minus the sum of row r's off-diagonal
+// entries, in increasing column.
+__device__ inline double laplacian_diagonal(const double* U, int32_t n, int32_t r) {
+    double acc = 0.0;
+    for (int32_t t = 0; t < n; ++t)
+        if (t != r) acc = acc + (r < t ? U[r * n + t] : U[t * n + r]);
+    return -acc;
+}
+
+// 3x3 block (R, S) of B B^T: acc[a][b] = sum over t, increasing, of
+// B[3R+a][t] B[3S+b][t] (rows past n count as zero).
+__device__ inline void spd_block(const double* B, int32_t ldb, int32_t n, int32_t R, int32_t S,
+                                 double (&acc)[3][3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) acc[a][b] = 0.0;
+    for (int32_t t = 0; t < n; ++t) {
+        double br[3], bs[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int32_t r = 3 * R + q, s = 3 * S + q;
+            br[q] = r < n ? B[r * ldb + t] : 0.0;
+            bs[q] = s < n ? B[s * ldb + t] : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) acc[a][b] = acc[a][b] + br[a] * bs[b];
+    }
+}
+
 // One 64-lane block per element; the uniforms in LDS (recipe 1: rows
 // padded by one value, so that lanes reading different rows hit different
 // banks), then the matrix.  Recipe 1 computes every entry, both triangles,
 // in 3x3 register blocks: K_sr sums the same products (B_st B_rt equals
 // B_rt B_st exactly) in the same order as K_rs, so the matrix is exactly
-// symmetric, and all 64 lanes have work (8 x 8 blocks for n = 24).
+// symmetric, and all 64 lanes have work (8 x 8 blocks for n = 24).  Where
+// the blocks fit one pass of the lanes (n <= 24) the matrix is staged in
+// LDS and stored by consecutive lanes, so that every store instruction
+// covers whole lines; the element matrices are written with non-temporal
+// stores (they are read once, by a later kernel).
+// MODE: 0 zero-row-sum, 1 SPD staged (n <= 24), 2 SPD with direct stores.
+template <int MODE>
 __global__ void __launch_bounds__(64)
-    k_gen(int recipe, int64_t n_elem, int32_t n, uint32_t k0, uint32_t k1, int64_t e0,
-          double* __restrict__ ke) {
+    k_gen(int64_t n_elem, int32_t n, uint32_t k0, uint32_t k1, int64_t e0, double* __restrict__ ke) {
+    constexpr int recipe = MODE == 0 ? 0 : 1;
     extern __shared__ double B[];  // [n][ldb]
     const int32_t n2 = n * n;
     const int32_t ldb = recipe == 0 ? n : n + 1;
     const int32_t nb = (n + 2) / 3;
+    const double dn = (double)n;
     for (int64_t e = blockIdx.x; e < n_elem; e += gridDim.x) {
         const uint64_t ge = (uint64_t)(e + e0);
         double* K = ke + e * (int64_t)n2;
         for (int32_t c = threadIdx.x; c * 4 < n2; c += 64) {
-            uint32_t w[4] = {(uint32_t)c, (uint32_t)ge, (uint32_t)(ge >> 32), (uint32_t)recipe};
-            philox4x32_10(w[0], w[1], w[2], w[3], k0, k1);
+            uint32_t w[4];
+            philox_block(c, ge, recipe, k0, k1, w);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int32_t i = c * 4 + q;
@@ -73,36 +132,18 @@ __global__ void __launch_bounds__(64)
             }
         }
         __syncthreads();
-        if (recipe == 0) {
+        if (MODE == 0) {
             for (int32_t i = threadIdx.x; i < n2; i += 64) {
                 const int32_t r = i / n, s = i - r * n;
-                if (r != s) {
-                    K[i] = r < s ? B[i] : B[s * n + r];
-                } else {
-                    double acc = 0.0;
-                    for (int32_t t = 0; t < n; ++t)
-                        if (t != r) acc = acc + (r < t ? B[r * n + t] : B[t * n + r]);
-                    K[i] = -acc;
-                }
+                const double v = r == s ? laplacian_diagonal(B, n, r) : r < s ? B[i] : B[s * n + r];
+                __builtin_nontemporal_store(v, K + i);
             }
-        } else {
-            const double dn = (double)n;
-            for (int32_t bi = threadIdx.x; bi < nb * nb; bi += 64) {
-                const int32_t R = bi / nb, S = bi - R * nb;
-                double acc[3][3] = {};
-                for (int32_t t = 0; t < n; ++t) {
-                    double br[3], bs[3];
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) {
-                        const int32_t r = 3 * R + q, s = 3 * S + q;
-                        br[q] = r < n ? B[r * ldb + t] : 0.0;
-                        bs[q] = s < n ? B[s * ldb + t] : 0.0;
-                    }
-#pragma unroll
-                    for (int a = 0; a < 3; ++a)
-#pragma unroll
-                        for (int b = 0; b < 3; ++b) acc[a][b] = acc[a][b] + br[a] * bs[b];
-                }
+        } else if (MODE == 1) {
+            const int32_t bi = threadIdx.x, R = bi / nb, S = bi - R * nb;
+            double acc[3][3];
+            if (bi < nb * nb) spd_block(B, ldb, n, R, S, acc);
+            __syncthreads();  // every lane has read B; it now holds K
+            if (bi < nb * nb) {
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -111,11 +152,128 @@ __global__ void __launch_bounds__(64)
                         if (r < n && s < n) {
                             double v = acc[a][b] / dn;
                             if (r == s) v = v + 1.0;
-                            K[r * n + s] = v;
+                            B[r * n + s] = v;
+                        }
+                    }
+            }
+            __syncthreads();
+            for (int32_t i = threadIdx.x; i < n2; i += 64) __builtin_nontemporal_store(B[i], K + i);
+        } else {
+            for (int32_t bi = threadIdx.x; bi < nb * nb; bi += 64) {
+                const int32_t R = bi / nb, S = bi - R * nb;
+                double acc[3][3];
+                spd_block(B, ldb, n, R, S, acc);
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) {
+                        const int32_t r = 3 * R + a, s = 3 * S + b;
+                        if (r < n && s < n) {
+                            double v = acc[a][b] / dn;
+                            if (r == s) v = v + 1.0;
+                            __builtin_nontemporal_store(v, K + r * n + s);
                         }
                     }
             }
         }
+        __syncthreads();
+    }
+}
+
+// Zero-row-sum recipe for n*n <= 64: 64/L elements per 64-lane block,
+// L = 2^lpe_log2 >= n*n lanes per element; lane (g, i) draws entry i of
+// element g into LDS, then writes entry i of the matrix (consecutive lanes,
+// consecutive entries of consecutive elements where L = n*n).
+__global__ void __launch_bounds__(64)
+    k_gen_laplacian_small(int64_t n_elem, int32_t n, int32_t lpe_log2, uint32_t k0, uint32_t k1,
+                          int64_t e0, double* __restrict__ ke) {
+    __shared__ double U[64];
+    const int32_t n2 = n * n, G = 64 >> lpe_log2;
+    const int l = threadIdx.x, g = l >> lpe_log2, i = l & ((1 << lpe_log2) - 1);
+    const double* Ug = U + (g << lpe_log2);
+    for (int64_t eb = (int64_t)blockIdx.x * G; eb < n_elem; eb += (int64_t)gridDim.x * G) {
+        const int64_t e = eb + g;
+        const bool valid = e < n_elem && i < n2;
+        if (valid) U[l] = 2.0 * entry_uniform(i, (uint64_t)(e + e0), 0, k0, k1) - 1.0;
+        __syncthreads();
+        if (valid) {
+            const int32_t r = i / n, s = i - r * n;
+            const double v = r == s ? laplacian_diagonal(Ug, n, r) : r < s ? Ug[i] : Ug[s * n + r];
+            __builtin_nontemporal_store(v, ke + e * (int64_t)n2 + i);
+        }
+        __syncthreads();
+    }
+}
+
+// SPD recipe for n = 4m <= 40: only the m(m+1)/2 upper-triangle 4x4 blocks
+// of B B^T are summed, and each is written to both triangles (K_sr sums the
+// same products, in the same order, as K_rs).  G = 64 / (m(m+1)/2) elements
+// per 64-lane block (3 for n = 24, 63 of 64 lanes busy).  LDS holds each
+// element's B transposed (column t of B contiguous, so that a lane reads its
+// four rows' entries of column t as two 16-byte words), later the element's
+// K, which consecutive lanes store as whole lines.
+__global__ void __launch_bounds__(64)
+    k_gen_spd_upper(int64_t n_elem, int32_t n, uint32_t k0, uint32_t k1, int64_t e0,
+                    double* __restrict__ ke) {
+    extern __shared__ double L[];  // [G][n*n]
+    const int32_t m = n / 4, U = m * (m + 1) / 2, G = 64 / U, n2 = n * n, chunks = n2 / 4;
+    const double dn = (double)n;
+    const int l = threadIdx.x, g = l / U;
+    int32_t blk = l - g * U, R = 0;
+    while (R < m - 1 && blk >= m - R) {
+        blk -= m - R;
+        ++R;
+    }
+    const int32_t S = R + blk;
+    for (int64_t eb = (int64_t)blockIdx.x * G; eb < n_elem; eb += (int64_t)gridDim.x * G) {
+        const int32_t here = (int32_t)(n_elem - eb < G ? n_elem - eb : G);
+        for (int32_t x = l; x < here * chunks; x += 64) {
+            const int32_t j = x / chunks, c = x - j * chunks;
+            uint32_t w[4];
+            philox_block(c, (uint64_t)(eb + j + e0), 1, k0, k1, w);
+            double* Bt = L + j * n2;
+            const int32_t r = (4 * c) / n, s = 4 * c - r * n;  // four entries of row r
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Bt[(s + q) * n + r] = ((double)w[q] * kTwoM32 - 0.5) * kSqrt12;
+        }
+        __syncthreads();
+        const bool work = g < here;
+        double acc[4][4];
+        if (work) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+            const double* Bt = L + g * n2;
+            for (int32_t t = 0; t < n; ++t) {
+                const double2* pr = reinterpret_cast<const double2*>(Bt + t * n + 4 * R);
+                const double2* ps = reinterpret_cast<const double2*>(Bt + t * n + 4 * S);
+                const double2 r01 = pr[0], r23 = pr[1], s01 = ps[0], s23 = ps[1];
+                const double br[4] = {r01.x, r01.y, r23.x, r23.y};
+                const double bs[4] = {s01.x, s01.y, s23.x, s23.y};
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) acc[a][b] = acc[a][b] + br[a] * bs[b];
+            }
+        }
+        __syncthreads();  // every lane has read B; LDS now takes K
+        if (work) {
+            double* Kl = L + g * n2;
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int32_t r = 4 * R + a, s = 4 * S + b;
+                    double v = acc[a][b] / dn;
+                    if (r == s) v = v + 1.0;
+                    Kl[r * n + s] = v;
+                    if (R != S) Kl[s * n + r] = v;
+                }
+        }
+        __syncthreads();
+        double* out = ke + eb * (int64_t)n2;
+        for (int32_t i = l; i < here * n2; i += 64) __builtin_nontemporal_store(L[i], out + i);
         __syncthreads();
     }
 }
@@ -131,10 +289,30 @@ extern "C" int generate_ke(int recipe, int64_t n_elem, int32_t n, uint64_t seed,
     if (n_elem < 0 || n <= 0 || elem_offset < 0) FEASM_FAIL(FEASM_EINVAL, "generate_ke: bad size");
     if ((int64_t)n * (n + 1) * 8 > 64 * 1024) FEASM_FAIL(FEASM_ELIMIT, "generate_ke: n too large");
     if (n_elem == 0) return FEASM_OK;
+    if (recipe == 0 && n * n <= 64) {
+        int32_t lg = 0;
+        while ((1 << lg) < n * n) ++lg;
+        const int64_t per_block = 64 >> lg;
+        const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(n_elem, per_block), 1 << 20);
+        k_gen_laplacian_small<<<grid, 64, 0, stream>>>(n_elem, n, lg, (uint32_t)seed,
+                                                       (uint32_t)(seed >> 32), elem_offset, ke);
+        FEASM_HIP(hipGetLastError());
+        return FEASM_OK;
+    }
+    if (recipe == 1 && n % 4 == 0 && n <= 40) {
+        const int32_t m = n / 4, per_block = 64 / (m * (m + 1) / 2);
+        const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(n_elem, per_block), 1 << 20);
+        const size_t lds = (size_t)per_block * n * n * 8;
+        k_gen_spd_upper<<<grid, 64, lds, stream>>>(n_elem, n, (uint32_t)seed, (uint32_t)(seed >> 32),
+                                                   elem_offset, ke);
+        FEASM_HIP(hipGetLastError());
+        return FEASM_OK;
+    }
     const unsigned grid = (unsigned)std::min<int64_t>(n_elem, 1 << 20);
     const size_t lds = (size_t)n * (recipe == 0 ? n : n + 1) * 8;
-    k_gen<<<grid, 64, lds, stream>>>(recipe, n_elem, n, (uint32_t)seed, (uint32_t)(seed >> 32),
-                                     elem_offset, ke);
+    const int32_t nb = (n + 2) / 3;
+    auto kern = recipe == 0 ? k_gen<0> : nb * nb <= 64 ? k_gen<1> : k_gen<2>;
+    kern<<<grid, 64, lds, stream>>>(n_elem, n, (uint32_t)seed, (uint32_t)(seed >> 32), elem_offset, ke);
     FEASM_HIP(hipGetLastError());
     return FEASM_OK;
 }

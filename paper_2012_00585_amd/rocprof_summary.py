@@ -9,7 +9,9 @@ rocprofv3 writes a SQLite ("rocpd") database per run.  This module reads
   ``--copy-mib``), so the bytes are real bytes.
 
 and writes a short markdown summary with the numbers and the commands that
-produced them.  ``source_hash()`` fingerprints the HIP sources, so a reader
+produced them.  With ``--shares`` it writes instead each kernel's share of the
+summed kernel time of a trace (optionally of its busiest window,
+``--window-s``), e.g. for a serving run.  ``source_hash()`` fingerprints the HIP sources, so a reader
 can tell whether a summary still describes the current kernels.
 
     python -m paper_2012_00585_amd.rocprof_summary --trace T.db --fetch F.db \
@@ -19,6 +21,7 @@ can tell whether a summary still describes the current kernels.
 from __future__ import annotations
 
 import argparse
+import bisect
 import collections
 import glob
 import hashlib
@@ -169,6 +172,69 @@ def summarize(trace, fetch, write, kernel, copy_mib, workload, command, algorith
     return "\n".join(lines)
 
 
+def _short_name(name):
+    """Kernel identifier with its template arguments, without the namespace
+    and parameter list."""
+    m = re.search(r"(k_\w+)(<[^()]*>)?", name)
+    return m.group(1) + (m.group(2) or "") if m else name.split("(")[0][-60:]
+
+
+def shares(trace, window_s, command, workload, title=None):
+    """Each kernel's share of the summed kernel time, over the whole trace or
+    over the window of window_s seconds with the most dispatches (the
+    saturated part of a serving run), and how busy the device was there."""
+    c = sqlite3.connect(trace)
+    rows = list(c.execute("select name, start, end from kernels order by start"))
+    if not rows:
+        raise SystemExit("no kernels in trace")
+    lo, hi = 0, len(rows)
+    if window_s:
+        starts = [r[1] for r in rows]
+        w, step = int(window_s * 1e9), int(0.25e9)
+        best, t = (-1, 0, 0), rows[0][1]
+        while t <= rows[-1][2]:
+            a, b = bisect.bisect_left(starts, t), bisect.bisect_left(starts, t + w)
+            if b - a > best[0]:
+                best = (b - a, a, b)
+            t += step
+        _, lo, hi = best
+    sel = rows[lo:hi]
+    tot, cnt = collections.defaultdict(float), collections.Counter()
+    for name, s0, e0 in sel:
+        k = _short_name(name)
+        tot[k] += (e0 - s0) / 1e6
+        cnt[k] += 1
+    summed = sum(tot.values())
+    ivs = sorted((s0, e0) for _, s0, e0 in sel)
+    busy, cs, ce = 0, ivs[0][0], ivs[0][1]
+    for s0, e0 in ivs[1:]:
+        if s0 > ce:
+            busy, cs, ce = busy + ce - cs, s0, e0
+        else:
+            ce = max(ce, e0)
+    busy += ce - cs
+    span = ivs[-1][1] - ivs[0][0]
+    lines = [f"# {title or 'kernel time shares'} on {workload}", "",
+             f"source hash: {source_hash()}", "",
+             "Commands (run from the repository root on the GPU host):", ""]
+    lines += [f"    {x}" for x in command] + [""]
+    where = (f"the {window_s:g} s window with the most dispatches" if window_s
+             else "the whole trace")
+    lines.append(f"Over {where}: {len(sel)} dispatches, device busy (union of kernel "
+                 f"intervals) {busy / span:.3f} of {span / 1e6:.1f} ms; kernels of "
+                 f"concurrent streams overlap, so the summed time ({summed:.1f} ms) exceeds it.")
+    lines.append("")
+    lines.append("| kernel | summed ms | share | dispatches | mean us |")
+    lines.append("|---|---|---|---|---|")
+    for k, v in sorted(tot.items(), key=lambda x: -x[1]):
+        if v < 0.001 * summed:
+            continue
+        lines.append(f"| {k[:100]} | {v:.1f} | {100 * v / summed:.1f}% | {cnt[k]} | "
+                     f"{1e3 * v / cnt[k]:.1f} |")
+    lines.append("")
+    return "\n".join(lines)
+
+
 def read_traffic(path):
     """(traffic bytes per launch, source hash) from a summary, or (None, None)."""
     if not os.path.exists(path):
@@ -184,16 +250,25 @@ def main():
     ap.add_argument("--trace", required=True)
     ap.add_argument("--fetch")
     ap.add_argument("--write")
-    ap.add_argument("--kernel", required=True, help="regular expression of the kernel name")
+    ap.add_argument("--kernel", help="regular expression of the kernel name")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--workload", default="hex64")
     ap.add_argument("--command", action="append", default=[])
     ap.add_argument("--algorithmic-bytes", type=int)
     ap.add_argument("--title")
     ap.add_argument("--out")
+    ap.add_argument("--shares", action="store_true",
+                    help="kernel time shares of the trace instead of one kernel's summary")
+    ap.add_argument("--window-s", type=float, default=0.0,
+                    help="with --shares: the window of this many seconds with most dispatches")
     a = ap.parse_args()
-    text = summarize(a.trace, a.fetch, a.write, a.kernel, a.copy_mib, a.workload, a.command,
-                     a.algorithmic_bytes, a.title)
+    if a.shares:
+        text = shares(a.trace, a.window_s, a.command, a.workload, a.title)
+    else:
+        if not a.kernel:
+            ap.error("--kernel is required without --shares")
+        text = summarize(a.trace, a.fetch, a.write, a.kernel, a.copy_mib, a.workload, a.command,
+                         a.algorithmic_bytes, a.title)
     if a.out:
         with open(a.out, "w") as f:
             f.write(text)
