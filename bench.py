@@ -152,6 +152,10 @@ def main():
                     help="batch512: number of meshes (the mix is the first N of the 512)")
     ap.add_argument("--cpu-reps", type=int, default=3, help="0 skips the oracle baseline")
     ap.add_argument("--only", default="", help="comma-separated variants to time (default: all)")
+    ap.add_argument("--sections", default="reassembly,spmv",
+                    help="single-mesh workloads: the sections reported after the variants, "
+                         "comma-separated from reassembly, spmv (empty: none, e.g. for a "
+                         "profile of the assembly kernels alone)")
     ap.add_argument("--hex8-pipe", type=int, default=0,
                     help="hex8 workload: fused-kernel setting (0 auto, n blocks per CU, -1 off)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -254,29 +258,35 @@ def main():
             # of this method besides HBM bandwidth)
             variants[name]["atomic_adds_per_launch"] = w.n_elem * w.n * w.n
             variants[name]["atomic_adds_per_s"] = w.n_elem * w.n * w.n / (t_sc["mean"] * 1e-3)
-    log("[bench] value-only re-assembly latency")
+    sections = set(filter(None, args.sections.split(",")))
+    unknown = sections - {"reassembly", "spmv"}
+    if unknown:
+        raise SystemExit(f"--sections: unknown {sorted(unknown)}")
     reasm = {}
-    for name, fmt, sc in (("csr_atomic", feasm.FMT_CSR, A), ("crac_atomic", feasm.FMT_CRAC, A),
-                          ("csr_owner", feasm.FMT_CSR, O), ("crac_owner", feasm.FMT_CRAC, O)):
-        fn = (lambda f=fmt, c=sc: feasm.reassemble_values(p, f, ke_d, values, c))
-        reasm[name] = stats(time_calls(fn, max(reps, 50), args.warmup))
-        if sc == O:
-            nb = algorithmic_bytes(w, p, name.split("_")[0], "record")
-            reasm[name]["algorithmic_bytes"] = nb
-            reasm[name]["GBps"] = nb / (reasm[name]["mean"] * 1e-3) / 1e9
+    if "reassembly" in sections:
+        log("[bench] value-only re-assembly latency")
+        for name, fmt, sc in (("csr_atomic", feasm.FMT_CSR, A), ("crac_atomic", feasm.FMT_CRAC, A),
+                              ("csr_owner", feasm.FMT_CSR, O), ("crac_owner", feasm.FMT_CRAC, O)):
+            fn = (lambda f=fmt, c=sc: feasm.reassemble_values(p, f, ke_d, values, c))
+            reasm[name] = stats(time_calls(fn, max(reps, 50), args.warmup))
+            if sc == O:
+                nb = algorithmic_bytes(w, p, name.split("_")[0], "record")
+                reasm[name]["algorithmic_bytes"] = nb
+                reasm[name]["GBps"] = nb / (reasm[name]["mean"] * 1e-3) / 1e9
 
-    log("[bench] matrix-vector product y = G x")
-    xv = torch.randn(p.n_rows, dtype=torch.float64, device=dev)
-    yv = torch.empty_like(xv)
     spmv = {}
-    # values, the format's index arrays and x read once, y written once
-    for name, fn, index_bytes in (("csr", feasm.spmv_csr, (p.n_rows + 1) * 4 + p.nnz * 4),
-                                  ("crac", feasm.spmv_crac, (p.n_rows + 1) * 4 + p.n_ca * 4)):
-        st = stats(time_calls(lambda f=fn: f(p, values, xv, yv), max(reps, 50), args.warmup))
-        nb = p.nnz * 8 + index_bytes + 2 * p.n_rows * 8
-        st["algorithmic_bytes"] = nb
-        st["GBps"] = nb / (st["mean"] * 1e-3) / 1e9
-        spmv[name] = st
+    if "spmv" in sections:
+        log("[bench] matrix-vector product y = G x")
+        xv = torch.randn(p.n_rows, dtype=torch.float64, device=dev)
+        yv = torch.empty_like(xv)
+        # values, the format's index arrays and x read once, y written once
+        for name, fn, index_bytes in (("csr", feasm.spmv_csr, (p.n_rows + 1) * 4 + p.nnz * 4),
+                                      ("crac", feasm.spmv_crac, (p.n_rows + 1) * 4 + p.n_ca * 4)):
+            st = stats(time_calls(lambda f=fn: f(p, values, xv, yv), max(reps, 50), args.warmup))
+            nb = p.nnz * 8 + index_bytes + 2 * p.n_rows * 8
+            st["algorithmic_bytes"] = nb
+            st["GBps"] = nb / (st["mean"] * 1e-3) / 1e9
+            spmv[name] = st
 
     best = min(variants, key=lambda k: variants[k]["assemble_ms"]["mean"])
     step = full[best]
