@@ -205,36 +205,39 @@ __global__ void __launch_bounds__(64)
     }
 }
 
-// SPD recipe for n = 4m <= 40: only the m(m+1)/2 upper-triangle 4x4 blocks
-// of B B^T are summed, and each is written to both triangles (K_sr sums the
-// same products, in the same order, as K_rs).  G = 64 / (m(m+1)/2) elements
-// per 64-lane block (3 for n = 24, 63 of 64 lanes busy).  LDS holds each
-// element's B transposed (column t of B contiguous, so that a lane reads its
-// four rows' entries of column t as two 16-byte words), later the element's
-// K, which consecutive lanes store as whole lines.
+// SPD recipe for n = N = 4m <= 40: only the m(m+1)/2 upper-triangle 4x4
+// blocks of B B^T are summed, and each is written to both triangles (K_sr
+// sums the same products, in the same order, as K_rs).  G = 64 / (m(m+1)/2)
+// elements per 64-lane block (3 for N = 24, 63 of 64 lanes busy).  LDS holds
+// each element's B transposed (column t of B contiguous, so that a lane
+// reads its four rows' entries of column t as two 16-byte words), later the
+// element's K, which consecutive lanes store as whole lines.  Rows of both
+// are N + 2 values apart, so that the lanes writing one column of B, or one
+// column of a K block, fall on different banks.
+template <int N>
 __global__ void __launch_bounds__(64)
-    k_gen_spd_upper(int64_t n_elem, int32_t n, uint32_t k0, uint32_t k1, int64_t e0,
-                    double* __restrict__ ke) {
-    extern __shared__ double L[];  // [G][n*n]
-    const int32_t m = n / 4, U = m * (m + 1) / 2, G = 64 / U, n2 = n * n, chunks = n2 / 4;
-    const double dn = (double)n;
+    k_gen_spd_upper(int64_t n_elem, uint32_t k0, uint32_t k1, int64_t e0, double* __restrict__ ke) {
+    constexpr int M = N / 4, U = M * (M + 1) / 2, G = 64 / U, N2 = N * N, CH = N2 / 4;
+    constexpr int LD = N + 2, P = N * LD;  // row stride and element stride in LDS
+    extern __shared__ double L[];           // [G][N][LD]
+    const double dn = (double)N;
     const int l = threadIdx.x, g = l / U;
     int32_t blk = l - g * U, R = 0;
-    while (R < m - 1 && blk >= m - R) {
-        blk -= m - R;
+    while (R < M - 1 && blk >= M - R) {
+        blk -= M - R;
         ++R;
     }
     const int32_t S = R + blk;
     for (int64_t eb = (int64_t)blockIdx.x * G; eb < n_elem; eb += (int64_t)gridDim.x * G) {
         const int32_t here = (int32_t)(n_elem - eb < G ? n_elem - eb : G);
-        for (int32_t x = l; x < here * chunks; x += 64) {
-            const int32_t j = x / chunks, c = x - j * chunks;
+        for (int32_t x = l; x < here * CH; x += 64) {
+            const int32_t j = x / CH, c = x - j * CH;
             uint32_t w[4];
             philox_block(c, (uint64_t)(eb + j + e0), 1, k0, k1, w);
-            double* Bt = L + j * n2;
-            const int32_t r = (4 * c) / n, s = 4 * c - r * n;  // four entries of row r
+            double* Bt = L + j * P;
+            const int32_t r = (4 * c) / N, s = 4 * c - r * N;  // four entries of row r
 #pragma unroll
-            for (int q = 0; q < 4; ++q) Bt[(s + q) * n + r] = ((double)w[q] * kTwoM32 - 0.5) * kSqrt12;
+            for (int q = 0; q < 4; ++q) Bt[(s + q) * LD + r] = ((double)w[q] * kTwoM32 - 0.5) * kSqrt12;
         }
         __syncthreads();
         const bool work = g < here;
@@ -244,10 +247,10 @@ __global__ void __launch_bounds__(64)
             for (int a = 0; a < 4; ++a)
 #pragma unroll
                 for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-            const double* Bt = L + g * n2;
-            for (int32_t t = 0; t < n; ++t) {
-                const double2* pr = reinterpret_cast<const double2*>(Bt + t * n + 4 * R);
-                const double2* ps = reinterpret_cast<const double2*>(Bt + t * n + 4 * S);
+            const double* Bt = L + g * P;
+            for (int32_t t = 0; t < N; ++t) {
+                const double2* pr = reinterpret_cast<const double2*>(Bt + t * LD + 4 * R);
+                const double2* ps = reinterpret_cast<const double2*>(Bt + t * LD + 4 * S);
                 const double2 r01 = pr[0], r23 = pr[1], s01 = ps[0], s23 = ps[1];
                 const double br[4] = {r01.x, r01.y, r23.x, r23.y};
                 const double bs[4] = {s01.x, s01.y, s23.x, s23.y};
@@ -259,7 +262,7 @@ __global__ void __launch_bounds__(64)
         }
         __syncthreads();  // every lane has read B; LDS now takes K
         if (work) {
-            double* Kl = L + g * n2;
+            double* Kl = L + g * P;
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -267,15 +270,29 @@ __global__ void __launch_bounds__(64)
                     const int32_t r = 4 * R + a, s = 4 * S + b;
                     double v = acc[a][b] / dn;
                     if (r == s) v = v + 1.0;
-                    Kl[r * n + s] = v;
-                    if (R != S) Kl[s * n + r] = v;
+                    Kl[r * LD + s] = v;
+                    if (R != S) Kl[s * LD + r] = v;
                 }
         }
         __syncthreads();
-        double* out = ke + eb * (int64_t)n2;
-        for (int32_t i = l; i < here * n2; i += 64) __builtin_nontemporal_store(L[i], out + i);
+        double* out = ke + eb * (int64_t)N2;
+        for (int32_t i = l; i < here * N2; i += 64) {
+            const int32_t j = i / N2, w = i - j * N2, r = w / N, s = w - r * N;
+            __builtin_nontemporal_store(L[j * P + r * LD + s], out + i);
+        }
         __syncthreads();
     }
+}
+
+template <int N>
+int launch_spd_upper(int64_t n_elem, uint64_t seed, int64_t elem_offset, double* ke, hipStream_t stream) {
+    constexpr int M = N / 4, G = 64 / (M * (M + 1) / 2);
+    const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(n_elem, G), 1 << 20);
+    const size_t lds = (size_t)G * N * (N + 2) * 8;
+    k_gen_spd_upper<N><<<grid, 64, lds, stream>>>(n_elem, (uint32_t)seed, (uint32_t)(seed >> 32),
+                                                  elem_offset, ke);
+    FEASM_HIP(hipGetLastError());
+    return FEASM_OK;
 }
 
 }  // namespace
@@ -299,14 +316,15 @@ extern "C" int generate_ke(int recipe, int64_t n_elem, int32_t n, uint64_t seed,
         FEASM_HIP(hipGetLastError());
         return FEASM_OK;
     }
-    if (recipe == 1 && n % 4 == 0 && n <= 40) {
-        const int32_t m = n / 4, per_block = 64 / (m * (m + 1) / 2);
-        const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(n_elem, per_block), 1 << 20);
-        const size_t lds = (size_t)per_block * n * n * 8;
-        k_gen_spd_upper<<<grid, 64, lds, stream>>>(n_elem, n, (uint32_t)seed, (uint32_t)(seed >> 32),
-                                                   elem_offset, ke);
-        FEASM_HIP(hipGetLastError());
-        return FEASM_OK;
+    if (recipe == 1) {
+        switch (n) {
+            case 8: return launch_spd_upper<8>(n_elem, seed, elem_offset, ke, stream);
+            case 16: return launch_spd_upper<16>(n_elem, seed, elem_offset, ke, stream);
+            case 24: return launch_spd_upper<24>(n_elem, seed, elem_offset, ke, stream);
+            case 32: return launch_spd_upper<32>(n_elem, seed, elem_offset, ke, stream);
+            case 40: return launch_spd_upper<40>(n_elem, seed, elem_offset, ke, stream);
+            default: break;
+        }
     }
     const unsigned grid = (unsigned)std::min<int64_t>(n_elem, 1 << 20);
     const size_t lds = (size_t)n * (recipe == 0 ? n : n + 1) * 8;
