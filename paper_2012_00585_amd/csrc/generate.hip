@@ -180,10 +180,9 @@ __global__ void __launch_bounds__(64)
     }
 }
 
-// Zero-row-sum recipe for n*n <= 64: 64/L elements per 64-lane block,
-// L = 2^lpe_log2 >= n*n lanes per element; lane (g, i) draws entry i of
-// element g into LDS, then writes entry i of the matrix (consecutive lanes,
-// consecutive entries of consecutive elements where L = n*n).
+// Zero-row-sum recipe for the other n with n*n <= 64: 64/L elements per
+// 64-lane block, L = 2^lpe_log2 >= n*n lanes per element; lane (g, i) draws
+// entry i of element g into LDS, then writes entry i of the matrix.
 __global__ void __launch_bounds__(64)
     k_gen_laplacian_small(int64_t n_elem, int32_t n, int32_t lpe_log2, uint32_t k0, uint32_t k1,
                           int64_t e0, double* __restrict__ ke) {
@@ -203,6 +202,48 @@ __global__ void __launch_bounds__(64)
         }
         __syncthreads();
     }
+}
+
+// Zero-row-sum recipe for N = 2, 4, 8: lane (j, c) draws Philox block c of
+// element j (G = 64 / (N*N/4) elements per 64-lane block, each block drawn
+// once), then the lanes write the G matrices' entries in order, consecutive
+// lanes to consecutive addresses.
+template <int N>
+__global__ void __launch_bounds__(64)
+    k_gen_laplacian_blocks(int64_t n_elem, uint32_t k0, uint32_t k1, int64_t e0,
+                           double* __restrict__ ke) {
+    constexpr int N2 = N * N, CH = N2 / 4, G = 64 / CH;
+    __shared__ double U[G * N2];
+    const int l = threadIdx.x, j0 = l / CH, c0 = l - j0 * CH;
+    for (int64_t eb = (int64_t)blockIdx.x * G; eb < n_elem; eb += (int64_t)gridDim.x * G) {
+        const int32_t here = (int32_t)(n_elem - eb < G ? n_elem - eb : G);
+        if (j0 < here) {
+            uint32_t w[4];
+            philox_block(c0, (uint64_t)(eb + j0 + e0), 0, k0, k1, w);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) U[j0 * N2 + 4 * c0 + q] = 2.0 * ((double)w[q] * kTwoM32) - 1.0;
+        }
+        __syncthreads();
+        double* out = ke + eb * (int64_t)N2;
+        for (int32_t i = l; i < here * N2; i += 64) {
+            const int32_t j = i / N2, x = i - j * N2, r = x / N, s = x - r * N;
+            const double* Uj = U + j * N2;
+            const double v = r == s ? laplacian_diagonal(Uj, N, r) : r < s ? Uj[x] : Uj[s * N + r];
+            __builtin_nontemporal_store(v, out + i);
+        }
+        __syncthreads();
+    }
+}
+
+template <int N>
+int launch_laplacian_blocks(int64_t n_elem, uint64_t seed, int64_t elem_offset, double* ke,
+                            hipStream_t stream) {
+    constexpr int G = 64 / (N * N / 4);
+    const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(n_elem, G), 1 << 20);
+    k_gen_laplacian_blocks<N><<<grid, 64, 0, stream>>>(n_elem, (uint32_t)seed, (uint32_t)(seed >> 32),
+                                                       elem_offset, ke);
+    FEASM_HIP(hipGetLastError());
+    return FEASM_OK;
 }
 
 // SPD recipe for n = N = 4m <= 40: only the m(m+1)/2 upper-triangle 4x4
@@ -306,6 +347,14 @@ extern "C" int generate_ke(int recipe, int64_t n_elem, int32_t n, uint64_t seed,
     if (n_elem < 0 || n <= 0 || elem_offset < 0) FEASM_FAIL(FEASM_EINVAL, "generate_ke: bad size");
     if ((int64_t)n * (n + 1) * 8 > 64 * 1024) FEASM_FAIL(FEASM_ELIMIT, "generate_ke: n too large");
     if (n_elem == 0) return FEASM_OK;
+    if (recipe == 0) {
+        switch (n) {
+            case 2: return launch_laplacian_blocks<2>(n_elem, seed, elem_offset, ke, stream);
+            case 4: return launch_laplacian_blocks<4>(n_elem, seed, elem_offset, ke, stream);
+            case 8: return launch_laplacian_blocks<8>(n_elem, seed, elem_offset, ke, stream);
+            default: break;
+        }
+    }
     if (recipe == 0 && n * n <= 64) {
         int32_t lg = 0;
         while ((1 << lg) < n * n) ++lg;

@@ -30,7 +30,7 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-@pytest.mark.parametrize("recipe,n", [(0, 1), (0, 3), (0, 4), (0, 8), (0, 9),
+@pytest.mark.parametrize("recipe,n", [(0, 1), (0, 2), (0, 3), (0, 4), (0, 8), (0, 9),
                                       (1, 3), (1, 8), (1, 16), (1, 24), (1, 30), (1, 40)])
 def test_device_generator_matches_host_twin(feasm, recipe, n):
     seed, e0, E = 2 ** 33 + 17, 1000, 77
