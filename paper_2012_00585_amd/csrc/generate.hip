@@ -95,12 +95,13 @@ __device__ inline void spd_block(const double* B, int32_t ldb, int32_t n, int32_
     }
 }
 
-// One 64-lane block per element; the uniforms in LDS (recipe 1: rows
-// padded by one value, so that lanes reading different rows hit different
-// banks), then the matrix.  Recipe 1 computes every entry, both triangles,
-// in 3x3 register blocks: K_sr sums the same products (B_st B_rt equals
-// B_rt B_st exactly) in the same order as K_rs, so the matrix is exactly
-// symmetric, and all 64 lanes have work (8 x 8 blocks for n = 24).  Where
+// The sizes the kernels below are not compiled for (zero-row-sum with
+// n*n > 64, SPD with n not in {8, 16, 24, 32, 40}): one 64-lane block per
+// element; the uniforms in LDS (recipe 1: rows padded by one value, so that
+// lanes reading different rows hit different banks), then the matrix.
+// Recipe 1 computes every entry, both triangles, in 3x3 register blocks:
+// K_sr sums the same products (B_st B_rt equals B_rt B_st exactly) in the
+// same order as K_rs, so the matrix is exactly symmetric.  Where
 // the blocks fit one pass of the lanes (n <= 24) the matrix is staged in
 // LDS and stored by consecutive lanes, so that every store instruction
 // covers whole lines; the element matrices are written with non-temporal
