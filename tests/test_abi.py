@@ -84,6 +84,29 @@ def test_pattern_build_rejects_bad_arguments(lib):
     assert lib.pattern_build(dummy, 4, 4, 1, 9, 1, None, None) == -1
 
 
+def test_generate_ke_rejects_bad_arguments(lib):
+    """Argument checks of the workload generator, all taken before any device
+    call (an empty batch also returns before launching)."""
+    from paper_2012_00585_amd._lib import STATUS_NAMES
+
+    d = ctypes.c_void_p(0x1000)  # never dereferenced
+    cases = [
+        ((0, 4, 4, 1, 0, None), "FEASM_EINVAL"),   # null output
+        ((2, 4, 4, 1, 0, d), "FEASM_EINVAL"),      # unknown recipe
+        ((1, -1, 24, 1, 0, d), "FEASM_EINVAL"),    # negative count
+        ((1, 4, 0, 1, 0, d), "FEASM_EINVAL"),      # empty matrices
+        ((0, 4, 4, 1, -5, d), "FEASM_EINVAL"),     # negative element offset
+        ((1, 4, 91, 1, 0, d), "FEASM_ELIMIT"),     # 91*92*8 bytes > 64 KiB
+        ((0, 0, 4, 1, 0, d), "FEASM_OK"),          # nothing to generate
+        ((1, 0, 24, 1, 0, d), "FEASM_OK"),
+    ]
+    for args, want in cases:
+        rc = lib.generate_ke(*args, None)
+        assert STATUS_NAMES[rc] == want, (args, rc)
+        if want != "FEASM_OK":
+            assert lib.last_error()
+
+
 def test_numeric_calls_reject_null_handle(lib):
     d = ctypes.c_void_p(0x1000)
     assert lib.assemble_csr(None, d, d, 0, None) == -1
