@@ -228,9 +228,13 @@ def test_tet40_pattern_and_sampled_values(feasm, orc):
     ref = orc.rows(w.conn, 3, w.n_nodes, ke, rows)
     for fmt, sc in (("csr", feasm.SCATTER_ATOMIC), ("crac", feasm.SCATTER_ATOMIC),
                     ("csr", feasm.SCATTER_COLOURED), ("crac", feasm.SCATTER_COLOURED),
-                    ("csr", feasm.SCATTER_OWNER), ("crac", feasm.SCATTER_OWNER)):
+                    ("csr", feasm.SCATTER_OWNER), ("crac", feasm.SCATTER_OWNER),
+                    ("csr", feasm.SCATTER_SPIN), ("crac", feasm.SCATTER_SPIN)):
         fn = feasm.assemble_csr if fmt == "csr" else feasm.assemble_crac
+        say(f"[parity] tet40 {fmt} strategy {sc}")
         v = _np(fn(p, ke_d, scatter=sc))
+        if sc == feasm.SCATTER_SPIN:
+            assert p.spin_aborts() == 0
         g_all, o_all, a_all = [], [], []
         for i, (cols, ov, oa) in zip(rows, ref):
             assert (ci[rp[i]:rp[i + 1]] == cols).all()
