@@ -547,29 +547,19 @@ void orc_spmv_crac(const int64_t* crac_row_ptr, const int64_t* ca, int64_t n_row
  * (-1,-1), then the top face (zeta = +1) in the same order.  Shape function
  * N_a = (1 + xi_a xi)(1 + eta_a eta)(1 + zeta_a zeta) / 8.  Quadrature: the
  * 2x2x2 Gauss rule, points +-1/sqrt(3), weights 1, in the order xi fastest,
- * then eta, then zeta.  With J_ij = dx_i/dxi_j, C the cofactors of J and
- * g_a = J^-T grad_xi N_a (g_a,i = sum_j C_ij / det J * dN_a/dxi_j):
+ * then eta, then zeta.  With J_ij = dx_i/dxi_j and g_a = J^-T grad_xi N_a:
  *   d = 1 (Laplace, mat[0] = kappa):
  *       K_ab = sum_q kappa (g_a . g_b) det J
  *   d = 3 (isotropic elasticity, mat[0] = lambda, mat[1] = mu), local DOF
  *       3a + i:
  *       K_(a,i)(b,j) = sum_q [lambda g_a,i g_b,j + mu (g_a,j g_b,i +
  *                       delta_ij g_a . g_b)] det J
- * Evaluation order (each step one correctly rounded operation; fma(a, b, c)
- * rounds a*b + c once):
- *   J_ij = fma over a = 0..7 of (x_a,i, dN_a,j) starting from 0
- *   C_ij = fma(J_i1j1, J_i2j2, -(J_i1j2 * J_i2j1))  (i1 = i+1, i2 = i+2,
- *          j1 = j+1, j2 = j+2, mod 3)
- *   det  = fma(J_00, C_00, fma(J_01, C_01, J_02 * C_02))
- *   g_a,i = fma over j = 0..2 of (C_ij / det, dN_a,j) starting from 0
- *   dot  = fma(g_a,2, g_b,2, fma(g_a,1, g_b,1, g_a,0 * g_b,0))
- *   d = 1: K_ab += fma(kappa * det, dot, 0) i.e. (kappa * det) * dot
- *   d = 3: with l = lambda * det, m = mu * det:
- *          s = (i == j) ? m * dot : 0;  s = fma(m * g_a,j, g_b,i, s);
- *          s = fma(l * g_a,i, g_b,j, s);  K_(a,i)(b,j) += s
- * x holds the 8 nodes' coordinates (x[3a + i]); K is n x n row-major with
- * n = 8 d; kabs (optional) receives sum_q of the terms' absolute values per
- * entry, a bound for the rounding error of any other evaluation order.
+ * Each formula is evaluated as written, left to right, with a separately
+ * rounded multiply or add per operation (build without contraction); any
+ * other evaluation order, fused multiply-adds included, differs from it by
+ * rounding only.  x holds the 8 nodes' coordinates (x[3a + i]); K is n x n
+ * row-major with n = 8 d; kabs (optional) receives sum_q |each term| per
+ * entry, the scale of the rounding error of any other evaluation order.
  * Returns ORC_OK, or ORC_ERANGE if det J <= 0 at a quadrature point.     */
 static const int HEX8_REF[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
                                    {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
@@ -594,52 +584,49 @@ int orc_hex8_stiffness(const double* x, int32_t d, const double* mat, double* K,
             dN[a][1] = f[0] * HEX8_REF[a][1] * f[2] / 8.0;
             dN[a][2] = f[0] * f[1] * HEX8_REF[a][2] / 8.0;
         }
-        double J[3][3];
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) {
-                double s = 0.0;
-                for (int a = 0; a < 8; ++a)
-                    s = fma(x[3 * a + i], dN[a][j], s);
-                J[i][j] = s;
-            }
+        double J[3][3] = {{0}};
+        for (int a = 0; a < 8; ++a)
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j)
+                    J[i][j] += x[3 * a + i] * dN[a][j];
+        /* inverse by cofactors: Jinv = adj(J) / det J */
         double C[3][3];
         for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 3; ++j) {
                 const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
-                C[i][j] = fma(J[i1][j1], J[i2][j2], -(J[i1][j2] * J[i2][j1])); /* cofactor of J_ij */
+                C[i][j] = J[i1][j1] * J[i2][j2] - J[i1][j2] * J[i2][j1]; /* cofactor of J_ij */
             }
-        const double det = fma(J[0][0], C[0][0], fma(J[0][1], C[0][1], J[0][2] * C[0][2]));
+        const double det = J[0][0] * C[0][0] + J[0][1] * C[0][1] + J[0][2] * C[0][2];
         if (!(det > 0.0))
             return ORC_ERANGE;
+        /* g_a,i = sum_j (J^-1)_ji dN_a,j and (J^-1)_ji = C_ij / det */
         double g[8][3];
         for (int a = 0; a < 8; ++a)
             for (int i = 0; i < 3; ++i) {
                 double s = 0.0;
                 for (int j = 0; j < 3; ++j)
-                    s = fma(C[i][j] / det, dN[a][j], s);
+                    s += C[i][j] / det * dN[a][j];
                 g[a][i] = s;
             }
         for (int a = 0; a < 8; ++a)
             for (int b = 0; b < 8; ++b) {
-                const double dot = fma(g[a][2], g[b][2], fma(g[a][1], g[b][1], g[a][0] * g[b][0]));
+                const double dot = g[a][0] * g[b][0] + g[a][1] * g[b][1] + g[a][2] * g[b][2];
                 if (d == 1) {
-                    const double t = (mat[0] * det) * dot;
+                    const double t = mat[0] * dot * det;
                     K[a * n + b] += t;
                     if (kabs)
                         kabs[a * n + b] += fabs(t);
                     continue;
                 }
-                const double l = mat[0] * det, m = mat[1] * det;
                 for (int i = 0; i < 3; ++i)
                     for (int j = 0; j < 3; ++j) {
-                        double s = i == j ? m * dot : 0.0;
-                        s = fma(m * g[a][j], g[b][i], s);
-                        s = fma(l * g[a][i], g[b][j], s);
+                        const double t1 = mat[0] * g[a][i] * g[b][j] * det;
+                        const double t2 = mat[1] * g[a][j] * g[b][i] * det;
+                        const double t3 = i == j ? mat[1] * dot * det : 0.0;
                         const int64_t p = (int64_t)(3 * a + i) * n + 3 * b + j;
-                        K[p] += s;
+                        K[p] += t1 + t2 + t3;
                         if (kabs)
-                            kabs[p] += fabs(l * g[a][i] * g[b][j]) + fabs(m * g[a][j] * g[b][i]) +
-                                       (i == j ? fabs(m * dot) : 0.0);
+                            kabs[p] += fabs(t1) + fabs(t2) + fabs(t3);
                     }
             }
     }

@@ -1,9 +1,14 @@
 """Device hexahedron stiffness and the fused element-matrix + assembly path
 against the oracle (GPU).
 
-Both sides evaluate the element matrix as the same sequence of correctly
-rounded operations and the fused assembly adds in element order, so
-element matrices and assembled values must equal the oracle's bit for bit.
+The oracle evaluates the textbook element formulas as written; the device
+uses its own fixed sequence of fused multiply-adds, so the two differ by
+rounding only.  Element matrices pass when |g - o| <= 1e-12 * kabs per entry
+(kabs = the sum of the absolute values of the terms, from the oracle), and
+assembled values against the oracle's assembly of K with the bound
+assembled from kabs.  Inside the device, the fused path and the two-pass
+path (element matrices, then the row-owned assembly) evaluate the same
+sequence and add in element order, so they must agree bit for bit.
 """
 import sys
 
@@ -11,6 +16,7 @@ import numpy as np
 import pytest
 import torch
 
+from tests._checks import assert_values_close
 from fe_inputs import matrices, meshes
 
 pytestmark = pytest.mark.gpu
@@ -81,24 +87,31 @@ PIPE = [0, 1, -1]
 
 @pytest.mark.parametrize("d", [1, 3])
 @pytest.mark.parametrize("name,make", MESHES, ids=[m[0] for m in MESHES])
-def test_element_matrices_and_fused_assembly_bit_exact(feasm, orc, name, make, d):
+def test_element_matrices_and_fused_assembly(feasm, orc, name, make, d):
     conn, nn, x = make()
     say(f"[hex8] {name} d={d}")
     p, xd, md, mat = _case(feasm, conn, nn, x, d, seed=5)
-    K, _ = orc.hex8_matrices(conn, x, d, mat)
-    kd = _np(feasm.hex8_element_matrices(p, xd, md))
-    assert (kd == K).all()
+    K, KA = orc.hex8_matrices(conn, x, d, mat)
+    kd_t = feasm.hex8_element_matrices(p, xd, md)
+    kd = _np(kd_t)
+    assert_values_close(kd.ravel(), K.ravel(), KA.ravel(), what="element matrices")
     rp, ci = orc.pattern(conn, d, nn)
-    ov, _ = orc.assemble(conn, d, K, rp, ci)
+    ov, _ = orc.assemble(conn, d, K, rp, ci, with_abs=False)
+    oa, _ = orc.assemble(conn, d, KA, rp, ci, with_abs=False)  # terms of every entry: >= 0
+    # the device's two-pass result: its element matrices, assembled in element order
+    two_pass = _np(feasm.assemble_crac(p, kd_t, scatter=feasm.SCATTER_OWNER))
+    assert_values_close(two_pass, ov, oa, what="two-pass values")
     for pipe in PIPE:
         p.tune(feasm.TUNE_HEX8_PIPE, pipe)
         for fmt in (feasm.FMT_CSR, feasm.FMT_CRAC):
             say(f"[hex8] {name} d={d} pipe={pipe} fmt={fmt}")
             v = _np(feasm.assemble_hex8(p, fmt, xd, md))
-            assert (v == ov).all(), (pipe, fmt)
+            assert_values_close(v, ov, oa, what=f"fused values pipe={pipe} fmt={fmt}")
+            assert (v == two_pass).all(), ("fused != two-pass", pipe, fmt)
             acc = torch.full((p.nnz,), 2.0, dtype=torch.float64, device="cuda")
             feasm.assemble_hex8(p, fmt, xd, md, acc, accumulate=True)
-            assert (_np(acc) == ov + 2.0).all(), (pipe, fmt)
+            assert_values_close(_np(acc), ov + 2.0, oa + 2.0, what="accumulated fused values")
+            assert (_np(acc) == two_pass + 2.0).all(), (pipe, fmt)
     p.free()
 
 
@@ -108,19 +121,26 @@ def test_hex64_elasticity_full_size(feasm, orc):
     x = meshes.hex_coords(m, jitter=0.2, seed=11)
     say("[hex8] 64^3 elasticity, full size")
     p, xd, md, mat = _case(feasm, conn, nn, x, 3, seed=12)
-    K, _ = orc.hex8_matrices(conn, x, 3, mat, with_abs=False)
+    K, KA = orc.hex8_matrices(conn, x, 3, mat)
+    kd_t = feasm.hex8_element_matrices(p, xd, md)
+    assert_values_close(_np(kd_t).ravel(), K.ravel(), KA.ravel(), what="element matrices")
     rp, ci = orc.pattern(conn, 3, nn)
     ov, _ = orc.assemble(conn, 3, K, rp, ci, with_abs=False)
+    oa, _ = orc.assemble(conn, 3, KA, rp, ci, with_abs=False)
+    del K, KA
+    two_pass = _np(feasm.assemble_crac(p, kd_t, scatter=feasm.SCATTER_OWNER))
+    del kd_t
+    assert_values_close(two_pass, ov, oa, what="two-pass values")
     for pipe in PIPE:
         say(f"[hex8] 64^3 elasticity pipe={pipe}")
         p.tune(feasm.TUNE_HEX8_PIPE, pipe)
         v = _np(feasm.assemble_hex8(p, feasm.FMT_CRAC, xd, md))
-        assert (v == ov).all(), pipe
+        assert_values_close(v, ov, oa, what=f"fused values pipe={pipe}")
+        assert (v == two_pass).all(), pipe
     p.tune(feasm.TUNE_HEX8_PIPE, 0)
-    assert (_np(feasm.assemble_hex8(p, feasm.FMT_CSR, xd, md)) == ov).all()
-    # the two-pass path gives the same values
-    kd = feasm.hex8_element_matrices(p, xd, md)
-    assert (_np(feasm.assemble_crac(p, kd, scatter=feasm.SCATTER_OWNER)) == ov).all()
+    v = _np(feasm.assemble_hex8(p, feasm.FMT_CSR, xd, md))
+    assert_values_close(v, ov, oa, what="fused CSR values")
+    assert (v == two_pass).all()
     p.free()
 
 
