@@ -25,7 +25,8 @@
  *  - "dev" pointers are HIP device memory on the current device; "host"
  *    pointers are ordinary host memory.  Streams are hipStream_t (NULL is
  *    the legacy default stream).
- *  - Every call returns a feasm_status.  No C++ exception crosses the ABI.
+ *  - Every call returns a feasm_status.  No C++ exception crosses the ABI:
+ *    the host running out of memory inside a call gives FEASM_ENOMEM.
  *    last_error() returns a thread-local message for the latest failure.
  *  - Numeric calls are asynchronous on the given stream; pattern_build
  *    synchronises with its stream before returning.
@@ -47,7 +48,7 @@ enum feasm_status {
     FEASM_OK = 0,
     FEASM_EINVAL = -1,    /* bad argument (null pointer, non-positive size, unknown flag) */
     FEASM_ERANGE = -2,    /* a node id outside [0, n_nodes) */
-    FEASM_ENOMEM = -3,    /* device allocation failed */
+    FEASM_ENOMEM = -3,    /* device or host memory allocation failed */
     FEASM_EHIP = -4,      /* a HIP runtime call failed */
     FEASM_EOVERFLOW = -5, /* nnz, CRAC length, rows or element entries reach 2^31 */
     FEASM_ELIMIT = -6     /* a documented implementation limit is exceeded */
@@ -111,7 +112,7 @@ enum {
  * Errors: EINVAL for bad arguments; ERANGE if a node id is out of range
  * (checked on the device, reported before returning); EOVERFLOW for int32
  * overflow of the pattern; ELIMIT if a node is shared by so many elements
- * that its candidate column list exceeds 32768 entries; ENOMEM; EHIP.
+ * that its candidate column list exceeds 8192 entries; ENOMEM; EHIP.
  * Synchronises `stream` before returning, so no asynchronous error is lost.
  */
 int pattern_build(const int32_t* conn, int64_t n_elem, int32_t nodes_per_elem,
@@ -278,8 +279,10 @@ int spmv_crac(const feasm_pattern* p, const double* values, const double* x, dou
  * g_a,i g_b,j + mu (g_a,j g_b,i + delta_ij g_a . g_b)] det J (local DOF
  * 3a + i), with the 2x2x2 Gauss rule (points +-1/sqrt(3), xi fastest), J_ij
  * = dx_i/dxi_j and g_a,i = sum_j C_ij / det J * dN_a/dxi_j (C: cofactors of
- * J).  Each entry is one fixed sequence of correctly rounded operations and
- * fused multiply-adds (fma(a,b,c) = a*b + c rounded once):
+ * J).  The device evaluates each entry as one fixed sequence of correctly
+ * rounded operations and fused multiply-adds (fma(a,b,c) = a*b + c rounded
+ * once), so its results are reproducible bit for bit and differ from any
+ * other evaluation of the same formulas by rounding only:
  *   J_ij  = fma over a = 0..7 of (x_a,i, dN_a,j), from 0
  *   C_ij  = fma(J_i1j1, J_i2j2, -(J_i1j2 * J_i2j1)), i1 = i+1, i2 = i+2 mod 3
  *   det   = fma(J_00, C_00, fma(J_01, C_01, J_02 * C_02))
@@ -300,7 +303,7 @@ int spmv_crac(const feasm_pattern* p, const double* values, const double* x, dou
  * incident element inside the row-owned assembly (no element matrices in
  * memory); fmt is FEASM_FMT_CSR or FEASM_FMT_CRAC.  Values are summed in
  * element order, as the sequential listing, so they equal a sequential
- * assembly of hex8_element_matrices' output bit for bit.
+ * (or row-owned) assembly of hex8_element_matrices' output bit for bit.
  * Asynchronous on `stream`; elements must not be inverted (det J > 0; not
  * checked).  Returns EINVAL for a null handle or buffer, k != 8, d not 1 or
  * 3, a format the handle lacks or an unknown flag; ELIMIT (assemble_hex8)

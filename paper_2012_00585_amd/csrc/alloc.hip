@@ -50,12 +50,14 @@ void dev_free(const Allocator& a, void* ptr, hipStream_t s) {
 }  // namespace feasm
 
 extern "C" int set_allocator(feasm_alloc_fn alloc, feasm_release_fn release, void* ctx) {
-    using namespace feasm;
-    if ((alloc == nullptr) != (release == nullptr))
-        FEASM_FAIL(FEASM_EINVAL, "set_allocator: give both alloc and release, or neither");
-    std::lock_guard<std::mutex> lock(g_alloc_mutex);
-    g_alloc.alloc = alloc;
-    g_alloc.release = release;
-    g_alloc.ctx = alloc ? ctx : nullptr;
-    return FEASM_OK;
+    return feasm::guarded("set_allocator", [&]() -> int {
+        using namespace feasm;
+        if ((alloc == nullptr) != (release == nullptr))
+            FEASM_FAIL(FEASM_EINVAL, "set_allocator: give both alloc and release, or neither");
+        std::lock_guard<std::mutex> lock(g_alloc_mutex);
+        g_alloc.alloc = alloc;
+        g_alloc.release = release;
+        g_alloc.ctx = alloc ? ctx : nullptr;
+        return FEASM_OK;
+    });
 }

@@ -467,154 +467,162 @@ void release_cache(feasm_pattern* p) {
 
 extern "C" int assemble_csr(const feasm_pattern* p, const double* ke, double* values, int scatter,
                             hipStream_t stream) {
-    return feasm::assemble_impl(p, 0, ke, values, scatter, nullptr, nullptr, stream,
-                                "assemble_csr");
+    return feasm::guarded("assemble_csr", [&]() -> int {
+        return feasm::assemble_impl(p, 0, ke, values, scatter, nullptr, nullptr, stream,
+                                    "assemble_csr");
+    });
 }
 
 extern "C" int assemble_crac(const feasm_pattern* p, const double* ke, double* values, int scatter,
                              hipStream_t stream) {
-    return feasm::assemble_impl(p, 1, ke, values, scatter, nullptr, nullptr, stream,
-                                "assemble_crac");
+    return feasm::guarded("assemble_crac", [&]() -> int {
+        return feasm::assemble_impl(p, 1, ke, values, scatter, nullptr, nullptr, stream,
+                                    "assemble_crac");
+    });
 }
 
 extern "C" int reassemble_values(feasm_pattern* p, int fmt, const double* ke, double* values,
                                  int scatter, hipStream_t stream) {
-    using namespace feasm;
-    if (!p) FEASM_FAIL(FEASM_EINVAL, "reassemble_values: null handle");
-    if (fmt != FEASM_FMT_CSR && fmt != FEASM_FMT_CRAC)
-        FEASM_FAIL(FEASM_EINVAL, "reassemble_values: fmt must be FEASM_FMT_CSR or FEASM_FMT_CRAC");
-    if (fmt == FEASM_FMT_CSR && !(p->flags & FEASM_BUILD_CSR))
-        FEASM_FAIL(FEASM_EINVAL, "reassemble_values: handle was built without CSR");
-    if (fmt == FEASM_FMT_CRAC && !(p->flags & FEASM_BUILD_CRAC))
-        FEASM_FAIL(FEASM_EINVAL, "reassemble_values: handle was built without CRAC");
-    // Both strategy families record their lookups on the first call and read
-    // the record afterwards instead of searching: the element-centric ones
-    // each element's (row node, run) offsets, the row-owned one the column
-    // offset of every element node in every owned row.
-    int strategy = scatter & ~FEASM_ACCUMULATE;
-    if (strategy == FEASM_SCATTER_AUTO) {
-        strategy = p->tune_strategy;
-        if (strategy == FEASM_SCATTER_AUTO ||
-            (strategy == FEASM_SCATTER_OWNER && !owner_fits(p, fmt)))
-            strategy = owner_fits(p, fmt) ? FEASM_SCATTER_OWNER : FEASM_SCATTER_ATOMIC;
-        scatter = strategy | (scatter & FEASM_ACCUMULATE);
-    }
-    if (strategy == FEASM_SCATTER_SPIN)
-        return assemble_impl(p, fmt, ke, values, scatter, nullptr, nullptr, stream,
-                             "reassemble_values");
-    if (strategy == FEASM_SCATTER_OWNER || strategy == FEASM_SCATTER_AUTO) {
-        if (!p->owner_map_valid) {
-            if (!p->owner_map) {
-                const int rc = dev_alloc_n(p->alloc, &p->owner_map, p->n_elem * p->k * p->k, stream,
-                                           "reassemble_values (lookup record)");
-                if (rc != FEASM_OK) return rc;
-            }
-            const int rc = build_owner_map(p, fmt, stream);
-            if (rc != FEASM_OK) return rc;
-            // the record is complete before any call, on any stream, may read it
-            FEASM_HIP(hipStreamSynchronize(stream));
-            p->owner_map_valid = true;
+    return feasm::guarded("reassemble_values", [&]() -> int {
+        using namespace feasm;
+        if (!p) FEASM_FAIL(FEASM_EINVAL, "reassemble_values: null handle");
+        if (fmt != FEASM_FMT_CSR && fmt != FEASM_FMT_CRAC)
+            FEASM_FAIL(FEASM_EINVAL, "reassemble_values: fmt must be FEASM_FMT_CSR or FEASM_FMT_CRAC");
+        if (fmt == FEASM_FMT_CSR && !(p->flags & FEASM_BUILD_CSR))
+            FEASM_FAIL(FEASM_EINVAL, "reassemble_values: handle was built without CSR");
+        if (fmt == FEASM_FMT_CRAC && !(p->flags & FEASM_BUILD_CRAC))
+            FEASM_FAIL(FEASM_EINVAL, "reassemble_values: handle was built without CRAC");
+        // Both strategy families record their lookups on the first call and read
+        // the record afterwards instead of searching: the element-centric ones
+        // each element's (row node, run) offsets, the row-owned one the column
+        // offset of every element node in every owned row.
+        int strategy = scatter & ~FEASM_ACCUMULATE;
+        if (strategy == FEASM_SCATTER_AUTO) {
+            strategy = p->tune_strategy;
+            if (strategy == FEASM_SCATTER_AUTO ||
+                (strategy == FEASM_SCATTER_OWNER && !owner_fits(p, fmt)))
+                strategy = owner_fits(p, fmt) ? FEASM_SCATTER_OWNER : FEASM_SCATTER_ATOMIC;
+            scatter = strategy | (scatter & FEASM_ACCUMULATE);
         }
-        return assemble_impl(p, fmt, ke, values, scatter, nullptr, nullptr, stream,
-                             "reassemble_values", p->owner_map);
-    }
-    if (p->cache && p->cache->valid && p->cache->fmt == fmt)
-        return assemble_impl(p, fmt, ke, values, scatter, p->cache->base, nullptr, stream,
-                             "reassemble_values");
-    if (p->cache) {
-        // queued calls may still read the old cache
-        FEASM_HIP(hipDeviceSynchronize());
-        release_cache(p);
-    }
-    p->cache = new (std::nothrow) OffsetCache();
-    if (!p->cache) FEASM_FAIL(FEASM_ENOMEM, "reassemble_values: out of host memory");
-    {
-        const int rc = dev_alloc_n(p->alloc, &p->cache->base, p->n_elem * p->k * p->k, stream,
-                                   "reassemble_values (lookup cache)");
+        if (strategy == FEASM_SCATTER_SPIN)
+            return assemble_impl(p, fmt, ke, values, scatter, nullptr, nullptr, stream,
+                                 "reassemble_values");
+        if (strategy == FEASM_SCATTER_OWNER || strategy == FEASM_SCATTER_AUTO) {
+            if (!p->owner_map_valid) {
+                if (!p->owner_map) {
+                    const int rc = dev_alloc_n(p->alloc, &p->owner_map, p->n_elem * p->k * p->k, stream,
+                                               "reassemble_values (lookup record)");
+                    if (rc != FEASM_OK) return rc;
+                }
+                const int rc = build_owner_map(p, fmt, stream);
+                if (rc != FEASM_OK) return rc;
+                // the record is complete before any call, on any stream, may read it
+                FEASM_HIP(hipStreamSynchronize(stream));
+                p->owner_map_valid = true;
+            }
+            return assemble_impl(p, fmt, ke, values, scatter, nullptr, nullptr, stream,
+                                 "reassemble_values", p->owner_map);
+        }
+        if (p->cache && p->cache->valid && p->cache->fmt == fmt)
+            return assemble_impl(p, fmt, ke, values, scatter, p->cache->base, nullptr, stream,
+                                 "reassemble_values");
+        if (p->cache) {
+            // queued calls may still read the old cache
+            FEASM_HIP(hipDeviceSynchronize());
+            release_cache(p);
+        }
+        p->cache = new (std::nothrow) OffsetCache();
+        if (!p->cache) FEASM_FAIL(FEASM_ENOMEM, "reassemble_values: out of host memory");
+        {
+            const int rc = dev_alloc_n(p->alloc, &p->cache->base, p->n_elem * p->k * p->k, stream,
+                                       "reassemble_values (lookup cache)");
+            if (rc != FEASM_OK) {
+                release_cache(p);
+                return rc;
+            }
+        }
+        p->cache->fmt = fmt;
+        const int rc = assemble_impl(p, fmt, ke, values, scatter, nullptr, p->cache->base, stream,
+                                     "reassemble_values");
         if (rc != FEASM_OK) {
             release_cache(p);
             return rc;
         }
-    }
-    p->cache->fmt = fmt;
-    const int rc = assemble_impl(p, fmt, ke, values, scatter, nullptr, p->cache->base, stream,
-                                 "reassemble_values");
-    if (rc != FEASM_OK) {
-        release_cache(p);
-        return rc;
-    }
-    // the record is complete before any call, on any stream, may read it
-    FEASM_HIP(hipStreamSynchronize(stream));
-    p->cache->valid = true;
-    return FEASM_OK;
+        // the record is complete before any call, on any stream, may read it
+        FEASM_HIP(hipStreamSynchronize(stream));
+        p->cache->valid = true;
+        return FEASM_OK;
+    });
 }
 
 extern "C" int pattern_tune(feasm_pattern* p, int key, int64_t value) {
-    if (!p) FEASM_FAIL(FEASM_EINVAL, "pattern_tune: null handle");
-    if (key == FEASM_TUNE_OWNER_BLOCKS_PER_CU) {
-        if (value < 0 || value > 64)
-            FEASM_FAIL(FEASM_EINVAL, "pattern_tune: owner blocks per CU must be in [0, 64]");
-        p->tune_owner_blocks_per_cu = (int32_t)value;
-        return FEASM_OK;
-    }
-    if (key == FEASM_TUNE_THREADS_PER_ELEM) {
-        if (value != 0 && value != 16 && value != 32 && value != 64 && value != 128 && value != 256)
-            FEASM_FAIL(FEASM_EINVAL, "pattern_tune: threads per element must be 16, 32, 64, 128 or 256");
-        if (value != 0 && (int64_t)p->n * p->n > value * 16)
-            FEASM_FAIL(FEASM_EINVAL, "pattern_tune: too few threads per element for this element size");
-        p->tune_atomic_tpe = (int32_t)value;
-        return FEASM_OK;
-    }
-    if (key == FEASM_TUNE_OWNER_ROWS) {
-        if (value != 0 && value != 1 && value != 2 && value != 4)
-            FEASM_FAIL(FEASM_EINVAL, "pattern_tune: owner rows per wavefront must be 1, 2 or 4");
-        p->tune_owner_rows = (int32_t)value;
-        return FEASM_OK;
-    }
-    if (key == FEASM_TUNE_OWNER_BATCH) {
-        if (value != 0 && value != 8 && value != 16)
-            FEASM_FAIL(FEASM_EINVAL, "pattern_tune: owner batch must be 8 or 16");
-        p->tune_owner_batch = (int32_t)value;
-        return FEASM_OK;
-    }
-    if (key == FEASM_TUNE_SPMV_CHUNK) {
-        if (value != 0 && value != 256 && value != 512 && value != 1024 && value != 2048)
-            FEASM_FAIL(FEASM_EINVAL, "pattern_tune: spmv chunk must be 256, 512, 1024 or 2048");
-        p->tune_spmv_chunk = (int32_t)value;
-        return FEASM_OK;
-    }
-    if (key == FEASM_TUNE_SPIN_LIMIT) {
-        if (value < -1 || value > ((int64_t)1 << 40))
-            FEASM_FAIL(FEASM_EINVAL, "pattern_tune: spin limit must be -1 or in [0, 2^40]");
-        p->tune_spin_limit = value;
-        return FEASM_OK;
-    }
-    if (key == FEASM_TUNE_HEX8_PIPE) {
-        if (value < -1 || value > 16)
-            FEASM_FAIL(FEASM_EINVAL, "pattern_tune: hex8 pipeline must be -1, 0 or 1..16 blocks per CU");
-        p->tune_hex8_pipe = (int32_t)value;
-        return FEASM_OK;
-    }
-    if (key == FEASM_TUNE_OWNER_PREFETCH) {
-        if (value != 0 && value != 1)
-            FEASM_FAIL(FEASM_EINVAL, "pattern_tune: owner prefetch must be 0 or 1");
-        p->tune_owner_prefetch = (int32_t)value;
-        return FEASM_OK;
-    }
-    if (key == FEASM_TUNE_OWNER_FLAT) {
-        if (value != -1 && value != 0 && value != 4 && value != 8 && value != 16)
-            FEASM_FAIL(FEASM_EINVAL,
-                       "pattern_tune: flat batch must be -1 (off), 0 (auto), 4, 8 or 16");
-        p->tune_owner_flat = (int32_t)value;
-        return FEASM_OK;
-    }
-    if (key == FEASM_TUNE_STRATEGY) {
-        if (value < FEASM_SCATTER_AUTO || value > FEASM_SCATTER_OWNER)
-            FEASM_FAIL(FEASM_EINVAL, "pattern_tune: unknown strategy");
-        if (value == FEASM_SCATTER_COLOURED && !(p->flags & FEASM_BUILD_COLOUR))
-            FEASM_FAIL(FEASM_EINVAL, "pattern_tune: coloured strategy needs FEASM_BUILD_COLOUR");
-        p->tune_strategy = (int32_t)value;
-        return FEASM_OK;
-    }
-    FEASM_FAIL(FEASM_EINVAL, "pattern_tune: unknown key");
+    return feasm::guarded("pattern_tune", [&]() -> int {
+        if (!p) FEASM_FAIL(FEASM_EINVAL, "pattern_tune: null handle");
+        if (key == FEASM_TUNE_OWNER_BLOCKS_PER_CU) {
+            if (value < 0 || value > 64)
+                FEASM_FAIL(FEASM_EINVAL, "pattern_tune: owner blocks per CU must be in [0, 64]");
+            p->tune_owner_blocks_per_cu = (int32_t)value;
+            return FEASM_OK;
+        }
+        if (key == FEASM_TUNE_THREADS_PER_ELEM) {
+            if (value != 0 && value != 16 && value != 32 && value != 64 && value != 128 && value != 256)
+                FEASM_FAIL(FEASM_EINVAL, "pattern_tune: threads per element must be 16, 32, 64, 128 or 256");
+            if (value != 0 && (int64_t)p->n * p->n > value * 16)
+                FEASM_FAIL(FEASM_EINVAL, "pattern_tune: too few threads per element for this element size");
+            p->tune_atomic_tpe = (int32_t)value;
+            return FEASM_OK;
+        }
+        if (key == FEASM_TUNE_OWNER_ROWS) {
+            if (value != 0 && value != 1 && value != 2 && value != 4)
+                FEASM_FAIL(FEASM_EINVAL, "pattern_tune: owner rows per wavefront must be 1, 2 or 4");
+            p->tune_owner_rows = (int32_t)value;
+            return FEASM_OK;
+        }
+        if (key == FEASM_TUNE_OWNER_BATCH) {
+            if (value != 0 && value != 8 && value != 16)
+                FEASM_FAIL(FEASM_EINVAL, "pattern_tune: owner batch must be 8 or 16");
+            p->tune_owner_batch = (int32_t)value;
+            return FEASM_OK;
+        }
+        if (key == FEASM_TUNE_SPMV_CHUNK) {
+            if (value != 0 && value != 256 && value != 512 && value != 1024 && value != 2048)
+                FEASM_FAIL(FEASM_EINVAL, "pattern_tune: spmv chunk must be 256, 512, 1024 or 2048");
+            p->tune_spmv_chunk = (int32_t)value;
+            return FEASM_OK;
+        }
+        if (key == FEASM_TUNE_SPIN_LIMIT) {
+            if (value < -1 || value > ((int64_t)1 << 40))
+                FEASM_FAIL(FEASM_EINVAL, "pattern_tune: spin limit must be -1 or in [0, 2^40]");
+            p->tune_spin_limit = value;
+            return FEASM_OK;
+        }
+        if (key == FEASM_TUNE_HEX8_PIPE) {
+            if (value < -1 || value > 16)
+                FEASM_FAIL(FEASM_EINVAL, "pattern_tune: hex8 pipeline must be -1, 0 or 1..16 blocks per CU");
+            p->tune_hex8_pipe = (int32_t)value;
+            return FEASM_OK;
+        }
+        if (key == FEASM_TUNE_OWNER_PREFETCH) {
+            if (value != 0 && value != 1)
+                FEASM_FAIL(FEASM_EINVAL, "pattern_tune: owner prefetch must be 0 or 1");
+            p->tune_owner_prefetch = (int32_t)value;
+            return FEASM_OK;
+        }
+        if (key == FEASM_TUNE_OWNER_FLAT) {
+            if (value != -1 && value != 0 && value != 4 && value != 8 && value != 16)
+                FEASM_FAIL(FEASM_EINVAL,
+                           "pattern_tune: flat batch must be -1 (off), 0 (auto), 4, 8 or 16");
+            p->tune_owner_flat = (int32_t)value;
+            return FEASM_OK;
+        }
+        if (key == FEASM_TUNE_STRATEGY) {
+            if (value < FEASM_SCATTER_AUTO || value > FEASM_SCATTER_OWNER)
+                FEASM_FAIL(FEASM_EINVAL, "pattern_tune: unknown strategy");
+            if (value == FEASM_SCATTER_COLOURED && !(p->flags & FEASM_BUILD_COLOUR))
+                FEASM_FAIL(FEASM_EINVAL, "pattern_tune: coloured strategy needs FEASM_BUILD_COLOUR");
+            p->tune_strategy = (int32_t)value;
+            return FEASM_OK;
+        }
+        FEASM_FAIL(FEASM_EINVAL, "pattern_tune: unknown key");
+    });
 }

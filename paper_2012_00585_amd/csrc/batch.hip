@@ -558,83 +558,93 @@ int create(feasm_batch* b, const feasm_pattern* const* patterns, int64_t count, 
 
 extern "C" int batch_create(const feasm_pattern* const* patterns, int64_t count, int fmt,
                             uint32_t flags, feasm_batch** out) {
-    using namespace feasm;
-    if (!out) FEASM_FAIL(FEASM_EINVAL, "batch_create: out is NULL");
-    *out = nullptr;
-    if (!patterns || count <= 0) FEASM_FAIL(FEASM_EINVAL, "batch_create: no meshes");
-    if (count > INT32_MAX) FEASM_FAIL(FEASM_EOVERFLOW, "batch_create: too many meshes");
-    if (fmt != FEASM_FMT_CSR && fmt != FEASM_FMT_CRAC)
-        FEASM_FAIL(FEASM_EINVAL, "batch_create: fmt must be FEASM_FMT_CSR or FEASM_FMT_CRAC");
-    if (flags & ~(uint32_t)(FEASM_ACCUMULATE | FEASM_BATCH_PER_MESH_GRAPH))
-        FEASM_FAIL(FEASM_EINVAL, "batch_create: unknown flag");
-    feasm_batch* b = new (std::nothrow) feasm_batch();
-    if (!b) FEASM_FAIL(FEASM_ENOMEM, "batch_create: out of host memory");
-    b->per_mesh_graph = (flags & FEASM_BATCH_PER_MESH_GRAPH) ? 1 : 0;
-    const int rc = create(b, patterns, count, fmt, (flags & FEASM_ACCUMULATE) ? 1 : 0);
-    if (rc != FEASM_OK) {
-        (void)hipDeviceSynchronize();
-        release_batch(b);
-        delete b;
-        return rc;
-    }
-    *out = b;
-    return FEASM_OK;
+    return feasm::guarded("batch_create", [&]() -> int {
+        using namespace feasm;
+        if (!out) FEASM_FAIL(FEASM_EINVAL, "batch_create: out is NULL");
+        *out = nullptr;
+        if (!patterns || count <= 0) FEASM_FAIL(FEASM_EINVAL, "batch_create: no meshes");
+        if (count > INT32_MAX) FEASM_FAIL(FEASM_EOVERFLOW, "batch_create: too many meshes");
+        if (fmt != FEASM_FMT_CSR && fmt != FEASM_FMT_CRAC)
+            FEASM_FAIL(FEASM_EINVAL, "batch_create: fmt must be FEASM_FMT_CSR or FEASM_FMT_CRAC");
+        if (flags & ~(uint32_t)(FEASM_ACCUMULATE | FEASM_BATCH_PER_MESH_GRAPH))
+            FEASM_FAIL(FEASM_EINVAL, "batch_create: unknown flag");
+        feasm_batch* b = new (std::nothrow) feasm_batch();
+        if (!b) FEASM_FAIL(FEASM_ENOMEM, "batch_create: out of host memory");
+        b->per_mesh_graph = (flags & FEASM_BATCH_PER_MESH_GRAPH) ? 1 : 0;
+        const int rc = create(b, patterns, count, fmt, (flags & FEASM_ACCUMULATE) ? 1 : 0);
+        if (rc != FEASM_OK) {
+            (void)hipDeviceSynchronize();
+            release_batch(b);
+            delete b;
+            return rc;
+        }
+        *out = b;
+        return FEASM_OK;
+    });
 }
 
 extern "C" int assemble_batch(feasm_batch* b, const double* const* ke, double* const* values,
                               hipStream_t stream) {
-    using namespace feasm;
-    if (!b) FEASM_FAIL(FEASM_EINVAL, "assemble_batch: null batch");
-    if (!ke || !values) FEASM_FAIL(FEASM_EINVAL, "assemble_batch: ke or values table is NULL");
-    bool changed = false;
-    for (int64_t m = 0; m < b->count; ++m) {
-        if (!ke[m] || !values[m])
-            FEASM_FAIL(FEASM_EINVAL, "assemble_batch: null pointer for mesh " + std::to_string(m));
-        changed |= ke[m] != b->h_ke[m] || values[m] != b->h_values[m];
-    }
-    if (b->per_mesh_graph) {
-        if (changed || !b->exec) {
+    return feasm::guarded("assemble_batch", [&]() -> int {
+        using namespace feasm;
+        if (!b) FEASM_FAIL(FEASM_EINVAL, "assemble_batch: null batch");
+        if (!ke || !values) FEASM_FAIL(FEASM_EINVAL, "assemble_batch: ke or values table is NULL");
+        bool changed = false;
+        for (int64_t m = 0; m < b->count; ++m) {
+            if (!ke[m] || !values[m])
+                FEASM_FAIL(FEASM_EINVAL, "assemble_batch: null pointer for mesh " + std::to_string(m));
+            changed |= ke[m] != b->h_ke[m] || values[m] != b->h_values[m];
+        }
+        if (b->per_mesh_graph) {
+            if (changed || !b->exec) {
+                b->h_ke.assign(ke, ke + b->count);
+                b->h_values.assign(values, values + b->count);
+                const int rc = capture_per_mesh(b, ke, values);
+                if (rc != FEASM_OK) return rc;
+            }
+            FEASM_HIP(hipGraphLaunch(b->exec, stream));
+            return FEASM_OK;
+        }
+        if (changed) {
+            // the tables are read by the graph's kernels: update them in stream order
             b->h_ke.assign(ke, ke + b->count);
             b->h_values.assign(values, values + b->count);
-            const int rc = capture_per_mesh(b, ke, values);
-            if (rc != FEASM_OK) return rc;
+            FEASM_HIP(hipMemcpyAsync(b->d_ke, b->h_ke.data(), sizeof(double*) * b->count,
+                                     hipMemcpyHostToDevice, stream));
+            FEASM_HIP(hipMemcpyAsync(b->d_values, b->h_values.data(), sizeof(double*) * b->count,
+                                     hipMemcpyHostToDevice, stream));
+            FEASM_HIP(hipStreamSynchronize(stream));  // host tables may change before the copy runs
         }
         FEASM_HIP(hipGraphLaunch(b->exec, stream));
         return FEASM_OK;
-    }
-    if (changed) {
-        // the tables are read by the graph's kernels: update them in stream order
-        b->h_ke.assign(ke, ke + b->count);
-        b->h_values.assign(values, values + b->count);
-        FEASM_HIP(hipMemcpyAsync(b->d_ke, b->h_ke.data(), sizeof(double*) * b->count,
-                                 hipMemcpyHostToDevice, stream));
-        FEASM_HIP(hipMemcpyAsync(b->d_values, b->h_values.data(), sizeof(double*) * b->count,
-                                 hipMemcpyHostToDevice, stream));
-        FEASM_HIP(hipStreamSynchronize(stream));  // host tables may change before the copy runs
-    }
-    FEASM_HIP(hipGraphLaunch(b->exec, stream));
-    return FEASM_OK;
+    });
 }
 
 extern "C" int batch_info(const feasm_batch* b, int32_t* n_phases, int64_t* n_tiles,
                           int64_t* grid, int32_t* paths) {
-    if (!b) FEASM_FAIL(FEASM_EINVAL, "batch_info: null batch");
-    if (n_phases) *n_phases = b->n_phases;
-    int64_t t = 0, g = 0;
-    for (const auto& L : b->launches) {
-        t += L.n_tiles;
-        g = std::max(g, L.grid);
-    }
-    if (n_tiles) *n_tiles = t;
-    if (grid) *grid = g;
-    if (paths)
-        for (int64_t m = 0; m < b->count; ++m) paths[m] = b->paths[m];
-    return FEASM_OK;
+    return feasm::guarded("batch_info", [&]() -> int {
+        if (!b) FEASM_FAIL(FEASM_EINVAL, "batch_info: null batch");
+        if (n_phases) *n_phases = b->n_phases;
+        int64_t t = 0, g = 0;
+        for (const auto& L : b->launches) {
+            t += L.n_tiles;
+            g = std::max(g, L.grid);
+        }
+        if (n_tiles) *n_tiles = t;
+        if (grid) *grid = g;
+        if (paths)
+            for (int64_t m = 0; m < b->count; ++m) paths[m] = b->paths[m];
+        return FEASM_OK;
+    });
 }
 
 extern "C" void batch_free(feasm_batch* b) {
-    if (!b) return;
-    (void)hipDeviceSynchronize();
-    feasm::release_batch(b);
-    delete b;
+    try {
+        if (!b) return;
+        (void)hipDeviceSynchronize();
+        feasm::release_batch(b);
+        delete b;
+    } catch (...) {
+        // nothing to report: the call has no status
+    }
 }

@@ -342,45 +342,47 @@ int launch_spd_upper(int64_t n_elem, uint64_t seed, int64_t elem_offset, double*
 
 extern "C" int generate_ke(int recipe, int64_t n_elem, int32_t n, uint64_t seed, int64_t elem_offset,
                            double* ke, hipStream_t stream) {
-    using namespace feasm;
-    if (!ke) FEASM_FAIL(FEASM_EINVAL, "generate_ke: ke is NULL");
-    if (recipe != 0 && recipe != 1) FEASM_FAIL(FEASM_EINVAL, "generate_ke: unknown recipe");
-    if (n_elem < 0 || n <= 0 || elem_offset < 0) FEASM_FAIL(FEASM_EINVAL, "generate_ke: bad size");
-    if ((int64_t)n * (n + 1) * 8 > 64 * 1024) FEASM_FAIL(FEASM_ELIMIT, "generate_ke: n too large");
-    if (n_elem == 0) return FEASM_OK;
-    if (recipe == 0) {
-        switch (n) {
-            case 2: return launch_laplacian_blocks<2>(n_elem, seed, elem_offset, ke, stream);
-            case 4: return launch_laplacian_blocks<4>(n_elem, seed, elem_offset, ke, stream);
-            case 8: return launch_laplacian_blocks<8>(n_elem, seed, elem_offset, ke, stream);
-            default: break;
+    return feasm::guarded("generate_ke", [&]() -> int {
+        using namespace feasm;
+        if (!ke) FEASM_FAIL(FEASM_EINVAL, "generate_ke: ke is NULL");
+        if (recipe != 0 && recipe != 1) FEASM_FAIL(FEASM_EINVAL, "generate_ke: unknown recipe");
+        if (n_elem < 0 || n <= 0 || elem_offset < 0) FEASM_FAIL(FEASM_EINVAL, "generate_ke: bad size");
+        if ((int64_t)n * (n + 1) * 8 > 64 * 1024) FEASM_FAIL(FEASM_ELIMIT, "generate_ke: n too large");
+        if (n_elem == 0) return FEASM_OK;
+        if (recipe == 0) {
+            switch (n) {
+                case 2: return launch_laplacian_blocks<2>(n_elem, seed, elem_offset, ke, stream);
+                case 4: return launch_laplacian_blocks<4>(n_elem, seed, elem_offset, ke, stream);
+                case 8: return launch_laplacian_blocks<8>(n_elem, seed, elem_offset, ke, stream);
+                default: break;
+            }
         }
-    }
-    if (recipe == 0 && n * n <= 64) {
-        int32_t lg = 0;
-        while ((1 << lg) < n * n) ++lg;
-        const int64_t per_block = 64 >> lg;
-        const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(n_elem, per_block), 1 << 20);
-        k_gen_laplacian_small<<<grid, 64, 0, stream>>>(n_elem, n, lg, (uint32_t)seed,
-                                                       (uint32_t)(seed >> 32), elem_offset, ke);
+        if (recipe == 0 && n * n <= 64) {
+            int32_t lg = 0;
+            while ((1 << lg) < n * n) ++lg;
+            const int64_t per_block = 64 >> lg;
+            const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(n_elem, per_block), 1 << 20);
+            k_gen_laplacian_small<<<grid, 64, 0, stream>>>(n_elem, n, lg, (uint32_t)seed,
+                                                           (uint32_t)(seed >> 32), elem_offset, ke);
+            FEASM_HIP(hipGetLastError());
+            return FEASM_OK;
+        }
+        if (recipe == 1) {
+            switch (n) {
+                case 8: return launch_spd_upper<8>(n_elem, seed, elem_offset, ke, stream);
+                case 16: return launch_spd_upper<16>(n_elem, seed, elem_offset, ke, stream);
+                case 24: return launch_spd_upper<24>(n_elem, seed, elem_offset, ke, stream);
+                case 32: return launch_spd_upper<32>(n_elem, seed, elem_offset, ke, stream);
+                case 40: return launch_spd_upper<40>(n_elem, seed, elem_offset, ke, stream);
+                default: break;
+            }
+        }
+        const unsigned grid = (unsigned)std::min<int64_t>(n_elem, 1 << 20);
+        const size_t lds = (size_t)n * (recipe == 0 ? n : n + 1) * 8;
+        const int32_t nb = (n + 2) / 3;
+        auto kern = recipe == 0 ? k_gen<0> : nb * nb <= 64 ? k_gen<1> : k_gen<2>;
+        kern<<<grid, 64, lds, stream>>>(n_elem, n, (uint32_t)seed, (uint32_t)(seed >> 32), elem_offset, ke);
         FEASM_HIP(hipGetLastError());
         return FEASM_OK;
-    }
-    if (recipe == 1) {
-        switch (n) {
-            case 8: return launch_spd_upper<8>(n_elem, seed, elem_offset, ke, stream);
-            case 16: return launch_spd_upper<16>(n_elem, seed, elem_offset, ke, stream);
-            case 24: return launch_spd_upper<24>(n_elem, seed, elem_offset, ke, stream);
-            case 32: return launch_spd_upper<32>(n_elem, seed, elem_offset, ke, stream);
-            case 40: return launch_spd_upper<40>(n_elem, seed, elem_offset, ke, stream);
-            default: break;
-        }
-    }
-    const unsigned grid = (unsigned)std::min<int64_t>(n_elem, 1 << 20);
-    const size_t lds = (size_t)n * (recipe == 0 ? n : n + 1) * 8;
-    const int32_t nb = (n + 2) / 3;
-    auto kern = recipe == 0 ? k_gen<0> : nb * nb <= 64 ? k_gen<1> : k_gen<2>;
-    kern<<<grid, 64, lds, stream>>>(n_elem, n, (uint32_t)seed, (uint32_t)(seed >> 32), elem_offset, ke);
-    FEASM_HIP(hipGetLastError());
-    return FEASM_OK;
+    });
 }

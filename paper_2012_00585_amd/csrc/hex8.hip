@@ -637,49 +637,53 @@ int launch_hex8(const feasm_pattern* p, Hex8Args A, size_t lds, hipStream_t s) {
 
 extern "C" int hex8_element_matrices(const feasm_pattern* p, const double* coords,
                                      const double* material, double* ke, hipStream_t stream) {
-    using namespace feasm;
-    int rc = check_hex8(p, coords, material, "hex8_element_matrices");
-    if (rc != FEASM_OK) return rc;
-    if (!ke) FEASM_FAIL(FEASM_EINVAL, "hex8_element_matrices: null ke");
-    if (p->n_elem == 0) return FEASM_OK;
-    Hex8Args A = hex8_args(p, coords, material);
-    A.ke = ke;
-    const unsigned blocks = (unsigned)ceil_div(p->n_elem, 8);
-    if (p->d == 1)
-        k_hex8_ke<1><<<blocks, 64, 0, stream>>>(A);
-    else
-        k_hex8_ke<3><<<blocks, 64, 0, stream>>>(A);
-    FEASM_HIP(hipGetLastError());
-    return FEASM_OK;
+    return feasm::guarded("hex8_element_matrices", [&]() -> int {
+        using namespace feasm;
+        int rc = check_hex8(p, coords, material, "hex8_element_matrices");
+        if (rc != FEASM_OK) return rc;
+        if (!ke) FEASM_FAIL(FEASM_EINVAL, "hex8_element_matrices: null ke");
+        if (p->n_elem == 0) return FEASM_OK;
+        Hex8Args A = hex8_args(p, coords, material);
+        A.ke = ke;
+        const unsigned blocks = (unsigned)ceil_div(p->n_elem, 8);
+        if (p->d == 1)
+            k_hex8_ke<1><<<blocks, 64, 0, stream>>>(A);
+        else
+            k_hex8_ke<3><<<blocks, 64, 0, stream>>>(A);
+        FEASM_HIP(hipGetLastError());
+        return FEASM_OK;
+    });
 }
 
 extern "C" int assemble_hex8(const feasm_pattern* p, int fmt, const double* coords,
                              const double* material, double* values, int flags,
                              hipStream_t stream) {
-    using namespace feasm;
-    int rc = check_hex8(p, coords, material, "assemble_hex8");
-    if (rc != FEASM_OK) return rc;
-    if (!values) FEASM_FAIL(FEASM_EINVAL, "assemble_hex8: null values");
-    if (fmt != FEASM_FMT_CSR && fmt != FEASM_FMT_CRAC)
-        FEASM_FAIL(FEASM_EINVAL, "assemble_hex8: fmt must be FEASM_FMT_CSR or FEASM_FMT_CRAC");
-    if (fmt == FEASM_FMT_CSR && !(p->flags & FEASM_BUILD_CSR))
-        FEASM_FAIL(FEASM_EINVAL, "assemble_hex8: handle was built without CSR");
-    if (fmt == FEASM_FMT_CRAC && !(p->flags & FEASM_BUILD_CRAC))
-        FEASM_FAIL(FEASM_EINVAL, "assemble_hex8: handle was built without CRAC");
-    if ((flags & ~FEASM_ACCUMULATE) != 0) FEASM_FAIL(FEASM_EINVAL, "assemble_hex8: unknown flag");
-    if (p->n_nodes == 0) return FEASM_OK;
-    Hex8Args A = hex8_args(p, coords, material);
-    A.values = values;
-    A.accumulate = (flags & FEASM_ACCUMULATE) ? 1 : 0;
-    const int d = p->d;
-    A.acc_doubles = d * d * p->max_deg;
-    A.idx_ints = fmt == FEASM_FMT_CSR ? d * p->max_deg : 2 * p->max_deg + 2;
-    const size_t lds = sizeof(double) * (64 * kGeo + 8 * d * 8 * d + (size_t)A.acc_doubles) +
-                       sizeof(int32_t) * ((size_t)A.idx_ints + 64);
-    if (lds > 64 * 1024)
-        FEASM_FAIL(FEASM_ELIMIT, "assemble_hex8: node rows too long for the LDS accumulator");
-    if (fmt == FEASM_FMT_CSR)
-        return d == 1 ? launch_hex8<kCSR, 1>(p, A, lds, stream) : launch_hex8<kCSR, 3>(p, A, lds, stream);
-    return d == 1 ? launch_hex8<kCRAC, 1>(p, A, lds, stream) : launch_hex8<kCRAC, 3>(p, A, lds, stream);
+    return feasm::guarded("assemble_hex8", [&]() -> int {
+        using namespace feasm;
+        int rc = check_hex8(p, coords, material, "assemble_hex8");
+        if (rc != FEASM_OK) return rc;
+        if (!values) FEASM_FAIL(FEASM_EINVAL, "assemble_hex8: null values");
+        if (fmt != FEASM_FMT_CSR && fmt != FEASM_FMT_CRAC)
+            FEASM_FAIL(FEASM_EINVAL, "assemble_hex8: fmt must be FEASM_FMT_CSR or FEASM_FMT_CRAC");
+        if (fmt == FEASM_FMT_CSR && !(p->flags & FEASM_BUILD_CSR))
+            FEASM_FAIL(FEASM_EINVAL, "assemble_hex8: handle was built without CSR");
+        if (fmt == FEASM_FMT_CRAC && !(p->flags & FEASM_BUILD_CRAC))
+            FEASM_FAIL(FEASM_EINVAL, "assemble_hex8: handle was built without CRAC");
+        if ((flags & ~FEASM_ACCUMULATE) != 0) FEASM_FAIL(FEASM_EINVAL, "assemble_hex8: unknown flag");
+        if (p->n_nodes == 0) return FEASM_OK;
+        Hex8Args A = hex8_args(p, coords, material);
+        A.values = values;
+        A.accumulate = (flags & FEASM_ACCUMULATE) ? 1 : 0;
+        const int d = p->d;
+        A.acc_doubles = d * d * p->max_deg;
+        A.idx_ints = fmt == FEASM_FMT_CSR ? d * p->max_deg : 2 * p->max_deg + 2;
+        const size_t lds = sizeof(double) * (64 * kGeo + 8 * d * 8 * d + (size_t)A.acc_doubles) +
+                           sizeof(int32_t) * ((size_t)A.idx_ints + 64);
+        if (lds > 64 * 1024)
+            FEASM_FAIL(FEASM_ELIMIT, "assemble_hex8: node rows too long for the LDS accumulator");
+        if (fmt == FEASM_FMT_CSR)
+            return d == 1 ? launch_hex8<kCSR, 1>(p, A, lds, stream) : launch_hex8<kCSR, 3>(p, A, lds, stream);
+        return d == 1 ? launch_hex8<kCRAC, 1>(p, A, lds, stream) : launch_hex8<kCRAC, 3>(p, A, lds, stream);
+    });
 }
 

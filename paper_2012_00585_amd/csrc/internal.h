@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <exception>
 #include <string>
 #include <vector>
 
@@ -12,7 +13,26 @@
 namespace feasm {
 
 // ---------------------------------------------------------------- errors
-void set_error(const std::string& msg);
+void set_error(const std::string& msg) noexcept;
+// "who: what", without allocating when that fails.
+void set_error_for(const char* who, const char* what) noexcept;
+
+// Runs the body of a C entry point.  The library's own code reports errors
+// by status; the only exceptions that can reach here come from the standard
+// library's host containers and strings running out of memory, and they
+// become FEASM_ENOMEM instead of crossing the C ABI.
+template <typename F>
+int guarded(const char* who, F&& body) noexcept {
+    try {
+        return body();
+    } catch (const std::exception& ex) {
+        set_error_for(who, ex.what());
+        return FEASM_ENOMEM;
+    } catch (...) {
+        set_error_for(who, "unexpected C++ exception");
+        return FEASM_ENOMEM;
+    }
+}
 
 struct Status {
     int code = FEASM_OK;

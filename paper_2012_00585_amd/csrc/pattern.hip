@@ -471,82 +471,94 @@ void release_pattern(feasm_pattern* p) {
 extern "C" int pattern_build(const int32_t* conn, int64_t n_elem, int32_t nodes_per_elem,
                              int32_t dofs_per_node, int64_t n_nodes, uint32_t build_flags,
                              hipStream_t stream, feasm_pattern** out) {
-    using namespace feasm;
-    if (!out) FEASM_FAIL(FEASM_EINVAL, "pattern_build: out is NULL");
-    *out = nullptr;
-    if (!conn) FEASM_FAIL(FEASM_EINVAL, "pattern_build: conn is NULL");
-    if (n_elem <= 0 || nodes_per_elem <= 0 || dofs_per_node <= 0 || n_nodes <= 0)
-        FEASM_FAIL(FEASM_EINVAL, "pattern_build: n_elem, nodes_per_elem, dofs_per_node and "
-                                 "n_nodes must be positive");
-    if (build_flags & ~(uint32_t)(FEASM_BUILD_CSR | FEASM_BUILD_CRAC | FEASM_BUILD_COLOUR))
-        FEASM_FAIL(FEASM_EINVAL, "pattern_build: unknown build flag");
-    if (!(build_flags & (FEASM_BUILD_CSR | FEASM_BUILD_CRAC)))
-        FEASM_FAIL(FEASM_EINVAL, "pattern_build: request FEASM_BUILD_CSR and/or FEASM_BUILD_CRAC");
-    if (n_elem * (int64_t)nodes_per_elem > INT32_MAX)
-        FEASM_FAIL(FEASM_EOVERFLOW, "pattern_build: n_elem * nodes_per_elem must be < 2^31");
-    if ((int64_t)dofs_per_node * n_nodes >= INT32_MAX)
-        FEASM_FAIL(FEASM_EOVERFLOW, "pattern_build: dofs_per_node * n_nodes must be < 2^31 - 1");
-    if ((int64_t)nodes_per_elem * dofs_per_node > 4096)
-        FEASM_FAIL(FEASM_ELIMIT, "pattern_build: element matrices larger than 4096 x 4096 are "
-                                 "not supported");
-    feasm_pattern* p = new (std::nothrow) feasm_pattern();
-    if (!p) FEASM_FAIL(FEASM_ENOMEM, "pattern_build: out of host memory");
-    (void)hipGetDevice(&p->device);
-    p->alloc = current_allocator();
-    p->n_elem = n_elem;
-    p->k = nodes_per_elem;
-    p->d = dofs_per_node;
-    p->n = nodes_per_elem * dofs_per_node;
-    p->n_nodes = n_nodes;
-    p->n_rows = (int64_t)dofs_per_node * n_nodes;
-    p->flags = build_flags;
-    const int rc = build(p, conn, stream);
-    if (rc != FEASM_OK) {
-        (void)hipStreamSynchronize(stream);
-        release_pattern(p);
-        delete p;
-        return rc;
-    }
-    *out = p;
-    return FEASM_OK;
+    return feasm::guarded("pattern_build", [&]() -> int {
+        using namespace feasm;
+        if (!out) FEASM_FAIL(FEASM_EINVAL, "pattern_build: out is NULL");
+        *out = nullptr;
+        if (!conn) FEASM_FAIL(FEASM_EINVAL, "pattern_build: conn is NULL");
+        if (n_elem <= 0 || nodes_per_elem <= 0 || dofs_per_node <= 0 || n_nodes <= 0)
+            FEASM_FAIL(FEASM_EINVAL, "pattern_build: n_elem, nodes_per_elem, dofs_per_node and "
+                                     "n_nodes must be positive");
+        if (build_flags & ~(uint32_t)(FEASM_BUILD_CSR | FEASM_BUILD_CRAC | FEASM_BUILD_COLOUR))
+            FEASM_FAIL(FEASM_EINVAL, "pattern_build: unknown build flag");
+        if (!(build_flags & (FEASM_BUILD_CSR | FEASM_BUILD_CRAC)))
+            FEASM_FAIL(FEASM_EINVAL, "pattern_build: request FEASM_BUILD_CSR and/or FEASM_BUILD_CRAC");
+        if (n_elem * (int64_t)nodes_per_elem > INT32_MAX)
+            FEASM_FAIL(FEASM_EOVERFLOW, "pattern_build: n_elem * nodes_per_elem must be < 2^31");
+        if ((int64_t)dofs_per_node * n_nodes >= INT32_MAX)
+            FEASM_FAIL(FEASM_EOVERFLOW, "pattern_build: dofs_per_node * n_nodes must be < 2^31 - 1");
+        if ((int64_t)nodes_per_elem * dofs_per_node > 4096)
+            FEASM_FAIL(FEASM_ELIMIT, "pattern_build: element matrices larger than 4096 x 4096 are "
+                                     "not supported");
+        feasm_pattern* p = new (std::nothrow) feasm_pattern();
+        if (!p) FEASM_FAIL(FEASM_ENOMEM, "pattern_build: out of host memory");
+        (void)hipGetDevice(&p->device);
+        p->alloc = current_allocator();
+        p->n_elem = n_elem;
+        p->k = nodes_per_elem;
+        p->d = dofs_per_node;
+        p->n = nodes_per_elem * dofs_per_node;
+        p->n_nodes = n_nodes;
+        p->n_rows = (int64_t)dofs_per_node * n_nodes;
+        p->flags = build_flags;
+        const int rc = build(p, conn, stream);
+        if (rc != FEASM_OK) {
+            (void)hipStreamSynchronize(stream);
+            release_pattern(p);
+            delete p;
+            return rc;
+        }
+        *out = p;
+        return FEASM_OK;
+    });
 }
 
 extern "C" void pattern_free(feasm_pattern* p) {
-    if (!p) return;
-    (void)hipDeviceSynchronize();
-    feasm::release_pattern(p);
-    delete p;
+    try {
+        if (!p) return;
+        (void)hipDeviceSynchronize();
+        feasm::release_pattern(p);
+        delete p;
+    } catch (...) {
+        // nothing to report: the call has no status
+    }
 }
 
 extern "C" int pattern_info(const feasm_pattern* p, int64_t* n_rows, int64_t* nnz, int64_t* n_ca,
                             int32_t* n_colours) {
-    if (!p) FEASM_FAIL(FEASM_EINVAL, "pattern_info: null handle");
-    if (n_rows) *n_rows = p->n_rows;
-    if (nnz) *nnz = p->nnz;
-    if (n_ca) *n_ca = (p->flags & FEASM_BUILD_CRAC) ? p->n_ca : 0;
-    if (n_colours) *n_colours = p->n_colours;
-    return FEASM_OK;
+    return feasm::guarded("pattern_info", [&]() -> int {
+        if (!p) FEASM_FAIL(FEASM_EINVAL, "pattern_info: null handle");
+        if (n_rows) *n_rows = p->n_rows;
+        if (nnz) *nnz = p->nnz;
+        if (n_ca) *n_ca = (p->flags & FEASM_BUILD_CRAC) ? p->n_ca : 0;
+        if (n_colours) *n_colours = p->n_colours;
+        return FEASM_OK;
+    });
 }
 
 extern "C" int pattern_arrays(const feasm_pattern* p, const int32_t** row_ptr,
                               const int32_t** col_idx, const int32_t** crac_row_ptr,
                               const int32_t** col_align) {
-    if (!p) FEASM_FAIL(FEASM_EINVAL, "pattern_arrays: null handle");
-    const bool csr = p->flags & FEASM_BUILD_CSR;
-    if (row_ptr) *row_ptr = csr ? p->row_ptr : nullptr;
-    if (col_idx) *col_idx = csr ? p->col_idx : nullptr;
-    if (crac_row_ptr) *crac_row_ptr = p->crac_row_ptr;
-    if (col_align) *col_align = p->ca;
-    return FEASM_OK;
+    return feasm::guarded("pattern_arrays", [&]() -> int {
+        if (!p) FEASM_FAIL(FEASM_EINVAL, "pattern_arrays: null handle");
+        const bool csr = p->flags & FEASM_BUILD_CSR;
+        if (row_ptr) *row_ptr = csr ? p->row_ptr : nullptr;
+        if (col_idx) *col_idx = csr ? p->col_idx : nullptr;
+        if (crac_row_ptr) *crac_row_ptr = p->crac_row_ptr;
+        if (col_align) *col_align = p->ca;
+        return FEASM_OK;
+    });
 }
 
 extern "C" int pattern_colouring(const feasm_pattern* p, const int64_t** colour_ptr,
                                  const int32_t** colour_elems, const int32_t** element_colour) {
-    if (!p) FEASM_FAIL(FEASM_EINVAL, "pattern_colouring: null handle");
-    if (!(p->flags & FEASM_BUILD_COLOUR))
-        FEASM_FAIL(FEASM_EINVAL, "pattern_colouring: handle was built without FEASM_BUILD_COLOUR");
-    if (colour_ptr) *colour_ptr = p->colour_ptr.data();
-    if (colour_elems) *colour_elems = p->colour_elems;
-    if (element_colour) *element_colour = p->elem_colour;
-    return FEASM_OK;
+    return feasm::guarded("pattern_colouring", [&]() -> int {
+        if (!p) FEASM_FAIL(FEASM_EINVAL, "pattern_colouring: null handle");
+        if (!(p->flags & FEASM_BUILD_COLOUR))
+            FEASM_FAIL(FEASM_EINVAL, "pattern_colouring: handle was built without FEASM_BUILD_COLOUR");
+        if (colour_ptr) *colour_ptr = p->colour_ptr.data();
+        if (colour_elems) *colour_elems = p->colour_elems;
+        if (element_colour) *element_colour = p->elem_colour;
+        return FEASM_OK;
+    });
 }

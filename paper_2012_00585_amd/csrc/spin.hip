@@ -188,15 +188,17 @@ int launch_spin(const feasm_pattern* pc, int fmt, const double* ke, double* valu
 }  // namespace feasm
 
 extern "C" int spin_aborts(feasm_pattern* p, int64_t* count) {
-    using namespace feasm;
-    if (!p || !count) FEASM_FAIL(FEASM_EINVAL, "spin_aborts: null argument");
-    *count = 0;
-    if (!p->spin_aborts) return FEASM_OK;
-    FEASM_HIP(hipDeviceSynchronize());
-    int32_t v = 0;
-    FEASM_HIP(hipMemcpy(&v, p->spin_aborts, sizeof(v), hipMemcpyDeviceToHost));
-    const int32_t zero = 0;
-    FEASM_HIP(hipMemcpy(p->spin_aborts, &zero, sizeof(zero), hipMemcpyHostToDevice));
-    *count = v;
-    return FEASM_OK;
+    return feasm::guarded("spin_aborts", [&]() -> int {
+        using namespace feasm;
+        if (!p || !count) FEASM_FAIL(FEASM_EINVAL, "spin_aborts: null argument");
+        *count = 0;
+        if (!p->spin_aborts) return FEASM_OK;
+        FEASM_HIP(hipDeviceSynchronize());
+        int32_t v = 0;
+        FEASM_HIP(hipMemcpy(&v, p->spin_aborts, sizeof(v), hipMemcpyDeviceToHost));
+        const int32_t zero = 0;
+        FEASM_HIP(hipMemcpy(p->spin_aborts, &zero, sizeof(zero), hipMemcpyHostToDevice));
+        *count = v;
+        return FEASM_OK;
+    });
 }

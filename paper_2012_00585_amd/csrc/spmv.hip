@@ -191,10 +191,14 @@ int spmv_impl(const feasm_pattern* p, int fmt, const double* values, const doubl
 
 extern "C" int spmv_csr(const feasm_pattern* p, const double* values, const double* x, double* y,
                         hipStream_t stream) {
-    return feasm::spmv_impl(p, 0, values, x, y, stream, "spmv_csr");
+    return feasm::guarded("spmv_csr", [&]() -> int {
+        return feasm::spmv_impl(p, 0, values, x, y, stream, "spmv_csr");
+    });
 }
 
 extern "C" int spmv_crac(const feasm_pattern* p, const double* values, const double* x, double* y,
                          hipStream_t stream) {
-    return feasm::spmv_impl(p, 1, values, x, y, stream, "spmv_crac");
+    return feasm::guarded("spmv_crac", [&]() -> int {
+        return feasm::spmv_impl(p, 1, values, x, y, stream, "spmv_crac");
+    });
 }
