@@ -16,16 +16,23 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
 
 CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c11"]
+# FEASM_ORACLE_SANITIZE=1: a separate build under AddressSanitizer and
+# UndefinedBehaviorSanitizer (the process must preload gcc's libasan and
+# libubsan); the tests run the oracle's pins against it.
+SANITIZE = os.environ.get("FEASM_ORACLE_SANITIZE", "") == "1"
+SAN_CFLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+              "-fno-sanitize-recover=all"]
+_LIB = os.path.join(_HERE, "liboracle_san.so" if SANITIZE else "liboracle.so")
 
 
 def build(force: bool = False) -> str:
     """Compile ``oracle.c`` with gcc into ``liboracle.so``."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"])
+        flags = [*CFLAGS, *SAN_CFLAGS] if SANITIZE else CFLAGS
+        subprocess.check_call(["gcc", *flags, _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
