@@ -81,20 +81,6 @@ def ke_small_int(E: int, n: int, seed: int = 0, lo: int = -8, hi: int = 8):
     return _mirror_upper(K)
 
 
-def values_on_pattern(rows, cols, seed: int = 0):
-    """A reproducible value for every stored entry (rows[q], cols[q]) of a
-    pattern, uniform in [-1, 1) and a function of (row, column, seed) only,
-    so two sides holding the same pattern (in any order) get the same
-    values.  SplitMix64 finaliser of (row * 2^32 + column) xor the seed."""
-    with np.errstate(over="ignore"):
-        z = (np.asarray(rows, dtype=np.uint64) << np.uint64(32)) | np.asarray(cols, dtype=np.uint64)
-        z = z ^ (np.uint64(seed) * np.uint64(0x9E3779B97F4A7C15))
-        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
-        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
-        z = z ^ (z >> np.uint64(31))
-    return (z >> np.uint64(11)).astype(np.float64) * 2.0 ** -52 - 1.0
-
-
 def hex_materials(E: int, d: int, seed: int = 0):
     """Per-element material parameters: ``[E]`` conductivities in [0.5, 2)
     for d = 1, ``[E, 2]`` Lame parameters (lambda in [0.5, 2), mu in

@@ -39,6 +39,8 @@ def main():
         "greedy_colours": int(nc),
         "row_ptr_sha_int64": __import__("hashlib").sha256(rp.astype(np.int64).tobytes()).hexdigest(),
         "col_idx_sha_int64": __import__("hashlib").sha256(ci.astype(np.int64).tobytes()).hexdigest(),
+        "crac_row_ptr_sha_int64": __import__("hashlib").sha256(
+            crp.astype(np.int64).tobytes()).hexdigest(),
         "ca_sha_int64": __import__("hashlib").sha256(ca.astype(np.int64).tobytes()).hexdigest(),
     }
     with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "tet40_counts.json"), "w") as f:

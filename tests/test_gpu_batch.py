@@ -177,63 +177,109 @@ def test_autotune_keeps_results(feasm, orc):
         p.free()
 
 
-def test_batch512_full_mix_sampled(feasm, orc):
+def _closed_form_nnz(sp):
+    """Structured Q1 meshes: (3N - 2)^2 for quads with N nodes per side and
+    d = 1, 9 (3N - 2)^3 for hexes with d = 3."""
+    N = sp.size + 1
+    return (3 * N - 2) ** 2 if sp.kind == "quad" else 9 * (3 * N - 2) ** 3
+
+
+def _row_sum_invariant(p, conn, ke, v, laplacian):
+    """On the device, with torch only: no value left unwritten, and the row
+    sums of G equal sum_e P_e^T (K_e 1) within 1e-12 of the same sum of
+    |K_e| row sums; zero for the zero-row-sum (Laplacian) matrices.  The
+    total of G equals the total of every element entry."""
+    assert not torch.isnan(v).any()
+    dev = v.device
+    E, k = conn.shape
+    d, n = p.dofs_per_node, p.n
+    rp, _ = p.csr()
+    counts = (rp[1:] - rp[:-1]).long()
+    rows = torch.repeat_interleave(torch.arange(p.n_rows, device=dev), counts)
+    g = torch.zeros(p.n_rows, dtype=torch.float64, device=dev).index_add_(0, rows, v[:p.nnz])
+    c = torch.from_numpy(conn).to(dev).long()
+    D = (d * c[:, :, None] + torch.arange(d, device=dev)).reshape(-1)
+    K = ke.view(E, n, n)
+    ref = torch.zeros_like(g).index_add_(0, D, K.sum(2).reshape(-1))
+    bound = 1e-12 * torch.zeros_like(g).index_add_(0, D, K.abs().sum(2).reshape(-1))
+    assert bool(((g - ref).abs() <= bound).all())
+    if laplacian:
+        assert bool((g.abs() <= bound).all())
+    tot, kt, ka = v[:p.nnz].sum().item(), ke.sum().item(), ke.abs().sum().item()
+    assert abs(tot - kt) <= 1e-12 * ka
+
+
+# oracle results of sampled meshes of the mix, shared by both formats
+_MIX_REFS = {}
+
+
+@pytest.mark.parametrize("fmt", [1, 0], ids=["crac", "csr"])
+def test_batch512_full_mix(feasm, orc, fmt):
     """The full 512-mesh mix in the launch configurations the benchmark
     times (autotuned handles; persistent and per-mesh-graph batches), with
-    element matrices from the device generator; sampled meshes are checked
-    against the oracle fed with the generator's host twin.  Row-owned meshes
-    must match bit for bit, the others within the value tolerance."""
+    element matrices from the device generator.
+    * every mesh: nnz equals the structured closed form, no value is left
+      unwritten, and the row-sum and total invariants hold;
+    * one mesh per (kind, autotuner size class, kernel path), the smallest of
+      each, plus the largest of each kind: every value against the oracle
+      fed with the generator's host twin -- row-owned meshes bit for bit,
+      the others within the value tolerance."""
     from fe_inputs import configs
     from paper_2012_00585_amd import autotune
     from paper_2012_00585_amd.batch import Batch
 
     dev = torch.device("cuda:0")
     specs = configs.batch_mix()
-    say(f"[batch512] building {len(specs)} meshes")
+    say(f"[batch512] fmt={fmt}: building {len(specs)} meshes")
     flags = feasm.BUILD_CSR | feasm.BUILD_CRAC | feasm.BUILD_COLOUR
     pats, kes, vals, meta = [], [], [], []
     for sp in specs:
         conn, nn = meshes.quad_mesh(sp.size) if sp.kind == "quad" else meshes.hex_mesh(sp.size)
         p = feasm.pattern_build(torch.from_numpy(conn).to(dev), sp.dofs_per_node, nn, flags)
+        assert p.nnz == _closed_form_nnz(sp), sp
         recipe = feasm.RECIPE_LAPLACIAN if sp.kind == "quad" else feasm.RECIPE_SPD
         kes.append(feasm.generate_ke(recipe, p.n_elem, p.n, sp.seed))
         vals.append(torch.empty(p.nnz, dtype=torch.float64, device=dev))
         pats.append(p)
         meta.append((sp, conn, nn))
     torch.cuda.synchronize()
-    autotune.autotune(pats, kes, vals, feasm.FMT_CRAC, reps=2, warmup=1, log=say)
-    # sampled: the smallest and the largest of each kind, and two in between
-    by_size = sorted(range(len(specs)), key=lambda i: (specs[i].kind, pats[i].n_elem))
-    quads = [i for i in by_size if specs[i].kind == "quad"]
-    hexes = [i for i in by_size if specs[i].kind == "hex"]
-    sample = sorted({quads[0], quads[len(quads) // 2], quads[-1], hexes[0], hexes[len(hexes) // 2],
-                     hexes[-1]})
-    refs = {}
-    for i in sample:
-        sp, conn, nn = meta[i]
-        E, k = conn.shape
-        n = k * sp.dofs_per_node
-        twin = philox.ke_laplacian if sp.kind == "quad" else philox.ke_spd
-        ke = twin(E, n, sp.seed)
-        rp, ci = orc.pattern(conn, sp.dofs_per_node, nn)
-        refs[i] = orc.assemble(conn, sp.dofs_per_node, ke, rp, ci)
-    paths = None  # each mesh's kernel path, from the persistent batch
+    autotune.autotune(pats, kes, vals, fmt, reps=2, warmup=1, log=say)
+    paths = None
+    refs = _MIX_REFS
     for per_mesh_graph in (False, True):
-        say(f"[batch512] per_mesh_graph={per_mesh_graph}")
+        say(f"[batch512] fmt={fmt} per_mesh_graph={per_mesh_graph}")
         for v in vals:
             v.fill_(np.nan)
-        b = Batch(pats, fmt=feasm.FMT_CRAC, per_mesh_graph=per_mesh_graph)
-        b.assemble(kes, vals)
-        torch.cuda.synchronize()
+        b = Batch(pats, fmt=fmt, per_mesh_graph=per_mesh_graph)
         if paths is None:
             paths = b.info()["paths"]
-        for i in sample:
+            groups = {}
+            for i, sp in enumerate(specs):
+                groups.setdefault((sp.kind, autotune.size_class(pats[i]), paths[i]), []).append(i)
+            sample = {min(m, key=lambda i: pats[i].n_elem) for m in groups.values()}
+            for kind in ("quad", "hex"):
+                sample.add(max((i for i in range(len(specs)) if specs[i].kind == kind),
+                               key=lambda i: pats[i].n_elem))
+            say(f"[batch512] {len(groups)} (kind, class, path) groups; oracle on "
+                f"{len(sample)} meshes")
+            for i in sorted(sample - set(refs)):
+                sp, conn, nn = meta[i]
+                E, k = conn.shape
+                twin = philox.ke_laplacian if sp.kind == "quad" else philox.ke_spd
+                ke = twin(E, k * sp.dofs_per_node, sp.seed)
+                rp, ci = orc.pattern(conn, sp.dofs_per_node, nn)
+                refs[i] = orc.assemble(conn, sp.dofs_per_node, ke, rp, ci)
+        b.assemble(kes, vals)
+        torch.cuda.synchronize()
+        for i, (sp, conn, nn) in enumerate(meta):
+            _row_sum_invariant(pats[i], conn, kes[i], vals[i], sp.kind == "quad")
+        for i in sorted(sample):
             got = _np(vals[i])
             ov, oa = refs[i]
             if paths[i].startswith(("own", "rows")):  # row-owned: element order
-                assert (got == ov).all(), (i, specs[i], per_mesh_graph)
+                assert (got == ov).all(), (i, specs[i], paths[i], per_mesh_graph)
             else:
-                assert_values_close(got, ov, oa, what=f"mesh {i} {specs[i]}")
+                assert_values_close(got, ov, oa, what=f"mesh {i} {specs[i]} {paths[i]}")
         b.free()
     for p in pats:
         p.free()

@@ -85,30 +85,20 @@ def test_hex64_full_bit_exact(feasm, orc):
     p.free()
 
 
-def test_tet40_sampled_rows_bit_exact(feasm, orc):
-    """Full-size permuted tet10 mesh: values from a seeded function of
-    (row, column); the oracle computes 3000 sampled rows from its own
-    pattern rows."""
-    w = configs.tet40()
-    say("[spmv] tet40 full size, sampled rows")
+def test_tet40_full_bit_exact(feasm, orc, tet40_ref):
+    """Full-size permuted tet10 mesh: the oracle's assembled values, every
+    row of y through CSR and CRAC against the oracle's product."""
+    r = tet40_ref
+    say("[spmv] tet40 full size")
     dev = torch.device("cuda:0")
-    p = feasm.pattern_build(torch.from_numpy(w.conn).to(dev), 3, w.n_nodes,
+    p = feasm.pattern_build(torch.from_numpy(r.w.conn).to(dev), 3, r.w.n_nodes,
                             feasm.BUILD_CSR | feasm.BUILD_CRAC)
-    rp_d, ci_d = p.csr()
-    rows_d = torch.repeat_interleave(torch.arange(p.n_rows, device=dev),
-                                     (rp_d[1:] - rp_d[:-1]).long())
-    vals = matrices.values_on_pattern(_np(rows_d), _np(ci_d), seed=7)
     x = np.random.default_rng(8).standard_normal(p.n_rows)
-    vd, xd = torch.from_numpy(vals).to(dev), torch.from_numpy(x).to(dev)
-    ycsr, ycrac = _np(feasm.spmv_csr(p, vd, xd)), _np(feasm.spmv_crac(p, vd, xd))
-    sample = np.random.default_rng(1).choice(p.n_rows, size=3000, replace=False)
-    E, k = w.conn.shape
-    ke0 = np.zeros((E, k * 3, k * 3))  # only the oracle's pattern rows are used
-    ref_rows = orc.rows(w.conn, 3, w.n_nodes, ke0, sample)
-    for i, (cols, _, _) in zip(sample, ref_rows):
-        rv = matrices.values_on_pattern(np.full(cols.size, i), cols, seed=7)
-        yi, _ = orc.spmv_csr(np.array([0, cols.size]), cols, rv, x)
-        assert ycsr[i] == yi[0] and ycrac[i] == yi[0], i
+    y, _ = orc.spmv_csr(r.rp, r.ci, r.ov, x, with_abs=False)
+    vd, xd = torch.from_numpy(r.ov).to(dev), torch.from_numpy(x).to(dev)
+    for fn in (feasm.spmv_csr, feasm.spmv_crac):
+        got = _np(fn(p, vd, xd))
+        assert (got == y).all(), fn.__name__
     p.free()
 
 
