@@ -28,6 +28,13 @@
  *  - Every call returns a feasm_status.  No C++ exception crosses the ABI:
  *    the host running out of memory inside a call gives FEASM_ENOMEM.
  *    last_error() returns a thread-local message for the latest failure.
+ *  - Threads: calls on different handles (and batches) are independent.
+ *    Several threads may make numeric calls (assemble_*, reassemble_values,
+ *    spmv_*, assemble_hex8, hex8_element_matrices) on one handle at once;
+ *    the state those calls create on first use is created once, under a
+ *    lock of the handle.  pattern_tune, spin_aborts and pattern_free must
+ *    not overlap any other call on the same handle, and calls writing the
+ *    same values buffer race as usual.
  *  - Numeric calls are asynchronous on the given stream; pattern_build
  *    synchronises with its stream before returning.
  */
@@ -51,7 +58,9 @@ enum feasm_status {
     FEASM_ENOMEM = -3,    /* device or host memory allocation failed */
     FEASM_EHIP = -4,      /* a HIP runtime call failed */
     FEASM_EOVERFLOW = -5, /* nnz, CRAC length, rows or element entries reach 2^31 */
-    FEASM_ELIMIT = -6     /* a documented implementation limit is exceeded */
+    FEASM_ELIMIT = -6,    /* a documented implementation limit is exceeded */
+    FEASM_EINCOMPLETE = -7 /* spin_aborts: row-lock lanes gave up, so the results
+                              of those launches miss their rows' contributions */
 };
 
 /* pattern_build flags (bitwise or) */
@@ -318,7 +327,10 @@ int assemble_hex8(const feasm_pattern* p, int fmt, const double* coords, const d
  * Lanes of FEASM_SCATTER_SPIN launches on this handle that reached the spin
  * limit since the last call (their rows' contributions are missing from
  * those results); synchronises the device and clears the count.  0 when
- * the handle never ran that strategy.  EINVAL for a null argument.
+ * the handle never ran that strategy.  Returns FEASM_OK when the count is
+ * 0 and FEASM_EINCOMPLETE (with *count set) when it is not, so a caller of
+ * the asynchronous row-lock scatter learns here whether its results are
+ * complete.  EINVAL for a null argument.
  */
 int spin_aborts(feasm_pattern* p, int64_t* count);
 

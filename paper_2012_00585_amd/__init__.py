@@ -141,9 +141,12 @@ class Pattern:
         _lib.check(_lib.load().pattern_tune(self.handle, key, value), "pattern_tune")
 
     def spin_aborts(self) -> int:
-        """Row-lock lanes that gave up since the last call (synchronises)."""
+        """Row-lock lanes that gave up since the last call (synchronises);
+        the library reports a non-zero count with FEASM_EINCOMPLETE."""
         c = ctypes.c_int64()
-        _lib.check(_lib.load().spin_aborts(self.handle, ctypes.byref(c)), "spin_aborts")
+        rc = _lib.load().spin_aborts(self.handle, ctypes.byref(c))
+        if rc != _lib.FEASM_EINCOMPLETE:
+            _lib.check(rc, "spin_aborts")
         return c.value
 
     def free(self):

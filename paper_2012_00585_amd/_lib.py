@@ -20,7 +20,9 @@ STATUS_NAMES = {
     -4: "FEASM_EHIP",
     -5: "FEASM_EOVERFLOW",
     -6: "FEASM_ELIMIT",
+    -7: "FEASM_EINCOMPLETE",
 }
+FEASM_EINCOMPLETE = -7
 
 # Every function the header declares, with (restype, argtypes).
 P = ctypes.c_void_p

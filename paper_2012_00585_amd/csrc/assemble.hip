@@ -507,6 +507,8 @@ extern "C" int reassemble_values(feasm_pattern* p, int fmt, const double* ke, do
         if (strategy == FEASM_SCATTER_SPIN)
             return assemble_impl(p, fmt, ke, values, scatter, nullptr, nullptr, stream,
                                  "reassemble_values");
+        // the lookup records are created once, by whichever thread comes first
+        std::lock_guard<std::mutex> lazy(p->lazy_mu);
         if (strategy == FEASM_SCATTER_OWNER || strategy == FEASM_SCATTER_AUTO) {
             if (!p->owner_map_valid) {
                 if (!p->owner_map) {

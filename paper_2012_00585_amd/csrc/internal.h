@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <exception>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -137,6 +138,9 @@ struct feasm_pattern {
     bool owner_map_valid = false;
     int32_t* row_locks = nullptr;    // dev [n_rows]: row-lock scatter (zero between launches)
     int32_t* spin_aborts = nullptr;  // dev [1]: lanes that reached the spin limit
+    // Serialises the creation of the state above that numeric calls add on
+    // first use (owner_map, cache, row_locks) between threads sharing a handle.
+    mutable std::mutex lazy_mu;
 
     // tuning (0 = library default)
     int32_t tune_owner_blocks_per_cu = 0;  // >0: persistent row-owned grid of this size per CU

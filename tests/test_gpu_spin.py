@@ -5,6 +5,7 @@ Rows are summed in lock order, so values agree with the oracle within the
 per-entry reorder bound for real matrices and exactly for small-integer
 matrices; no lane may reach the spin limit.  The give-up path is exercised
 from the host with a spin limit of zero attempts."""
+import ctypes
 import sys
 
 import numpy as np
@@ -101,8 +102,14 @@ def test_give_up_path(feasm):
     p.tune(feasm.TUNE_SPIN_LIMIT, -1)
     v = _np(feasm.assemble_crac(p, ke, scatter=feasm.SCATTER_SPIN))
     assert (v == 0).all()
+    c = ctypes.c_int64()
+    assert feasm._lib.load().spin_aborts(p.handle, ctypes.byref(c)) == feasm._lib.FEASM_EINCOMPLETE
+    assert c.value == E * 24
+    assert feasm._lib.load().spin_aborts(p.handle, ctypes.byref(c)) == 0  # cleared by the read
+    assert c.value == 0
+    v = _np(feasm.assemble_crac(p, ke, scatter=feasm.SCATTER_SPIN))
     assert p.spin_aborts() == E * 24
-    assert p.spin_aborts() == 0  # cleared by the read
+    assert p.spin_aborts() == 0
     p.tune(feasm.TUNE_SPIN_LIMIT, 0)
     v = _np(feasm.assemble_crac(p, ke, scatter=feasm.SCATTER_SPIN))
     assert v.sum() == E * 24 * 24
