@@ -2,18 +2,27 @@
 // colour share no node, so a colour can be assembled in parallel without
 // synchronisation; the paper colours greedily).
 //
-// The greedy first-fit rule is kept -- an element takes the smallest colour
-// unused by its already-coloured neighbours -- but elements are coloured in
-// the parallel order of Jones and Plassmann: in each round, every uncoloured
-// element whose uncoloured neighbours all have lower priority colours
-// itself.  Priorities are a fixed hash of the element id, so the result is
-// deterministic.  "Coloured before this round" is read from a round stamp,
-// which makes each round independent of thread timing.
+// The result is exactly the sequential greedy colouring in element order:
+// element e takes the smallest colour not used by any element f < e that
+// shares a node with it.  That colour depends only on the colours of e's
+// smaller neighbours, so e can be coloured as soon as all of them are, and
+// the elements coloured at one time share no node.  The device runs the
+// greedy order as rounds over a frontier:
+//   * pred[e] counts the (element, shared node) incidences of e with smaller
+//     elements (a neighbour sharing two nodes counts twice);
+//   * the first frontier holds the elements with pred 0;
+//   * a round colours every frontier element from its smaller neighbours'
+//     colours, then takes one off pred of every larger neighbour per shared
+//     node; an element whose count reaches 0 joins the next frontier.
+// Structured meshes in lexicographic order get the paper's even 4 (quads)
+// and 8 (hexes) colours.  Rounds are launched in batches between host
+// checks; a round past the last frontier finds an empty one and does
+// nothing.
 //
 // Elements are then grouped by colour with a stable counting sort (per
 // wavefront counts, one scan, per-wavefront ranks), so each colour lists its
 // elements in increasing id.
-#include <climits>
+#include <algorithm>
 
 #include "internal.h"
 
@@ -21,54 +30,56 @@ namespace feasm {
 
 namespace {
 
-constexpr int32_t kUncoloured = INT_MAX;
-
-// MurmurHash3's 32-bit finaliser (Appleby), used as a fixed pseudo-random
-// priority; ties are broken by the element id.
-__device__ inline uint64_t priority(uint32_t e) {
-    uint32_t x = e;
-    x ^= x >> 16;
-    x *= 0x85ebca6bu;
-    x ^= x >> 13;
-    x *= 0xc2b2ae35u;
-    x ^= x >> 16;
-    return ((uint64_t)x << 32) | e;
-}
-
-__global__ void k_jp_round(const int32_t* __restrict__ conn, int32_t k, int64_t n_elem,
-                           const int64_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc_elem,
-                           int32_t* __restrict__ colour, int32_t* __restrict__ stamp, int32_t round,
-                           int32_t* __restrict__ remaining, int32_t* __restrict__ max_colour) {
+// pred[e] = incidences of e with smaller elements, summed over e's nodes.
+__global__ void k_pred_count(const int32_t* __restrict__ conn, int32_t k, int64_t n_elem,
+                             const int64_t* __restrict__ inc_ptr,
+                             const int32_t* __restrict__ inc_elem, int32_t* __restrict__ pred,
+                             int32_t* __restrict__ frontier, int32_t* __restrict__ count) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_elem;
          e += (int64_t)gridDim.x * blockDim.x) {
-        if (stamp[e] < round) continue;  // coloured in an earlier round
-        const uint64_t mine = priority((uint32_t)e);
-        bool ready = true;
-        for (int32_t a = 0; a < k && ready; ++a) {
+        int32_t c = 0;
+        for (int32_t a = 0; a < k; ++a) {
             const int32_t v = conn[e * k + a];
+            // incident elements are ascending within a node
             for (int64_t t = inc_ptr[v]; t < inc_ptr[v + 1]; ++t) {
-                const int32_t f = inc_elem[t];
-                if (f == e) continue;
-                if (stamp[f] >= round && priority((uint32_t)f) > mine) {
-                    ready = false;
-                    break;
-                }
+                if (inc_elem[t] >= e) break;
+                ++c;
             }
         }
-        if (!ready) {
-            atomicAdd(remaining, 1);
-            continue;
-        }
-        // smallest colour not used by a neighbour coloured before this round,
-        // searched 64 colours at a time
+        pred[e] = c;
+        if (c == 0) frontier[atomicAdd(count, 1)] = (int32_t)e;
+    }
+}
+
+// One greedy round.  counts[r % 3] holds this round's frontier size; the
+// next frontier is counted in counts[(r + 1) % 3]; counts[(r + 2) % 3] (read
+// by the previous round) is cleared for the round after next.
+__global__ void k_greedy_round(const int32_t* __restrict__ conn, int32_t k,
+                               const int64_t* __restrict__ inc_ptr,
+                               const int32_t* __restrict__ inc_elem, int32_t* __restrict__ colour,
+                               int32_t* __restrict__ pred, const int32_t* __restrict__ front_in,
+                               int32_t* __restrict__ front_out, int32_t* __restrict__ counts,
+                               int32_t round, int32_t* __restrict__ max_colour,
+                               unsigned long long* __restrict__ n_coloured) {
+    const int32_t cur = round % 3, nxt = (round + 1) % 3, clr = (round + 2) % 3;
+    const int32_t n = counts[cur];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        counts[clr] = 0;
+        if (n > 0) atomicAdd(n_coloured, (unsigned long long)n);
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t e = front_in[i];
+        const int32_t* ce = conn + (int64_t)e * k;
+        // smallest colour unused by the smaller neighbours, 64 colours at a time
         int32_t chosen = -1;
         for (int32_t base = 0; chosen < 0; base += 64) {
             uint64_t used = 0;
             for (int32_t a = 0; a < k; ++a) {
-                const int32_t v = conn[e * k + a];
+                const int32_t v = ce[a];
                 for (int64_t t = inc_ptr[v]; t < inc_ptr[v + 1]; ++t) {
                     const int32_t f = inc_elem[t];
-                    if (f == e || stamp[f] >= round) continue;
+                    if (f >= e) break;
                     const int32_t c = colour[f] - base;
                     if (c >= 0 && c < 64) used |= 1ull << c;
                 }
@@ -76,8 +87,16 @@ __global__ void k_jp_round(const int32_t* __restrict__ conn, int32_t k, int64_t 
             if (~used) chosen = base + __ffsll((unsigned long long)~used) - 1;
         }
         colour[e] = chosen;
-        stamp[e] = round;
         atomicMax(max_colour, chosen);
+        // release the larger neighbours, once per shared node
+        for (int32_t a = 0; a < k; ++a) {
+            const int32_t v = ce[a];
+            for (int64_t t = inc_ptr[v]; t < inc_ptr[v + 1]; ++t) {
+                const int32_t f = inc_elem[t];
+                if (f <= e) continue;
+                if (atomicSub(pred + f, 1) == 1) front_out[atomicAdd(counts + nxt, 1)] = f;
+            }
+        }
     }
 }
 
@@ -156,36 +175,48 @@ struct Buf {
 int build_colouring(feasm_pattern* p, hipStream_t s) {
     const int64_t E = p->n_elem;
     Buf tmp(p->alloc, s);
-    int32_t *stamp, *counters;
+    int32_t *pred, *front0, *front1, *counters;
+    unsigned long long* n_coloured;
     int rc = dev_alloc_n(p->alloc, &p->elem_colour, E, s, "pattern_build (colouring)");
     if (rc == FEASM_OK) rc = dev_alloc_n(p->alloc, &p->colour_elems, E, s, "pattern_build (colouring)");
-    if (rc == FEASM_OK) rc = tmp.alloc(&stamp, E);
-    if (rc == FEASM_OK) rc = tmp.alloc(&counters, 2);
+    if (rc == FEASM_OK) rc = tmp.alloc(&pred, E);
+    if (rc == FEASM_OK) rc = tmp.alloc(&front0, E);
+    if (rc == FEASM_OK) rc = tmp.alloc(&front1, E);
+    // counters[0..2]: frontier sizes by round mod 3; counters[3]: largest colour
+    if (rc == FEASM_OK) rc = tmp.alloc(&counters, 4);
+    if (rc == FEASM_OK) rc = tmp.alloc(&n_coloured, 1);
     if (rc != FEASM_OK) return rc;
-    k_fill_i32<<<grid(E, 256), 256, 0, s>>>(stamp, E, kUncoloured);
     k_fill_i32<<<grid(E, 256), 256, 0, s>>>(p->elem_colour, E, -1);
-    k_fill_i32<<<1, 64, 0, s>>>(counters, 2, 0);
+    k_fill_i32<<<1, 64, 0, s>>>(counters, 4, 0);
+    k_fill_i32<<<1, 64, 0, s>>>(reinterpret_cast<int32_t*>(n_coloured), 2, 0);
+    k_pred_count<<<grid(E, 256), 256, 0, s>>>(p->conn, p->k, E, p->inc_ptr, p->inc_elem, pred,
+                                              front0, counters);
     FEASM_HIP(hipGetLastError());
-    // rounds: counters[0] = elements left after the round, counters[1] = max colour
-    int32_t round = 0;
+    // the longest chain of neighbours in increasing element order bounds the
+    // rounds (a few hundred on the structured meshes); check every kBatch
+    constexpr int kBatch = 32;
+    const unsigned g = std::min(grid(E, 256), 2048u);
+    int64_t round = 0;
     for (;;) {
-        constexpr int kBatch = 4;
         for (int r = 0; r < kBatch; ++r, ++round) {
-            k_fill_i32<<<1, 64, 0, s>>>(counters, 1, 0);
-            k_jp_round<<<grid(E, 256), 256, 0, s>>>(p->conn, p->k, E, p->inc_ptr, p->inc_elem,
-                                                    p->elem_colour, stamp, round, counters,
-                                                    counters + 1);
+            int32_t* fin = (round & 1) ? front1 : front0;
+            int32_t* fout = (round & 1) ? front0 : front1;
+            k_greedy_round<<<g, 256, 0, s>>>(p->conn, p->k, p->inc_ptr, p->inc_elem,
+                                             p->elem_colour, pred, fin, fout, counters,
+                                             (int32_t)(round % 3), counters + 3, n_coloured);
         }
         FEASM_HIP(hipGetLastError());
-        int32_t h[2];
-        FEASM_HIP(hipMemcpyAsync(h, counters, sizeof(h), hipMemcpyDeviceToHost, s));
+        unsigned long long done = 0;
+        int32_t maxc = 0;
+        FEASM_HIP(hipMemcpyAsync(&done, n_coloured, sizeof(done), hipMemcpyDeviceToHost, s));
+        FEASM_HIP(hipMemcpyAsync(&maxc, counters + 3, sizeof(maxc), hipMemcpyDeviceToHost, s));
         FEASM_HIP(hipStreamSynchronize(s));
-        if (h[0] == 0) {
-            p->n_colours = h[1] + 1;
+        if ((int64_t)done == E) {
+            p->n_colours = maxc + 1;
             break;
         }
-        if (round > 4 * E + 8)
-            FEASM_FAIL(FEASM_EHIP, "colouring did not converge");  // unreachable: >= 1 element per round
+        if (round > E + kBatch)  // unreachable: every round colours at least one element
+            FEASM_FAIL(FEASM_EHIP, "colouring did not converge");
     }
     // stable grouping by colour
     const int64_t n_waves = ceil_div(E, 64);

@@ -84,9 +84,12 @@ def check_against_oracle(orc, conn, d, nn, ke, res, exact=False, owner_exact=Tru
     assert res["n_ca"] == ca.size
     assert (res["crac_row_ptr"] == crp).all()
     assert (res["ca"] == ca).all()
-    # colouring: valid, and the grouped list is a permutation sorted within colours
+    # colouring: valid, the sequential greedy colouring in element order, and
+    # the grouped list is a permutation sorted within colours
     nc = res["n_colours"]
     assert orc.colouring_valid(conn, nn, res["elem_colour"], nc)
+    gcol, gnc = orc.greedy_colour(conn, nn)
+    assert nc == gnc and (res["elem_colour"] == gcol).all()
     ptr = res["colour_ptr"]
     assert ptr[0] == 0 and ptr[-1] == conn.shape[0]
     ce = res["colour_elems"]
@@ -167,7 +170,9 @@ def test_quad64_workload(feasm, orc):
     ke = w.ke()
     res = run_device(feasm, w.conn, w.dofs_per_node, w.n_nodes, ke)
     assert res["nnz"] == 37249 and res["n_ca"] == 25092
-    assert res["n_colours"] >= 4
+    # structured quads: the paper's four even colours
+    assert res["n_colours"] == 4
+    assert np.diff(res["colour_ptr"]).tolist() == [1024] * 4
     check_against_oracle(orc, w.conn, w.dofs_per_node, w.n_nodes, ke, res)
     res["p"].free()
 
@@ -201,6 +206,9 @@ def test_hex64_pattern_and_values(feasm, orc, hex64):
         ("crac", feasm.SCATTER_COLOURED), ("csr", feasm.SCATTER_OWNER),
         ("crac", feasm.SCATTER_OWNER)])
     assert res["nnz"] == 64701513 and res["n_ca"] == 14527112
+    # structured hexahedra: eight even colours
+    assert res["n_colours"] == 8
+    assert np.diff(res["colour_ptr"]).tolist() == [32768] * 8
     check_against_oracle(orc, w.conn, 3, w.n_nodes, ke, res)
     res["p"].free()
 
@@ -209,44 +217,44 @@ def _sha(a):
     return hashlib.sha256(np.asarray(a, dtype=np.int64).tobytes()).hexdigest()
 
 
-def test_tet40_pattern_and_sampled_values(feasm, orc):
+def test_tet40_full(feasm, orc, tet40_ref):
+    """The permuted tet10 workload in full: pattern and CRAC arrays equal to
+    the oracle's, the colouring equal to the oracle's greedy colouring, and
+    every value of every strategy compared with the oracle's assembly."""
     g = json.load(open(os.path.join(GOLDEN, "tet40_counts.json")))
-    w = configs.tet40()
-    say("[parity] tet40 (permuted tet10): generating Ke (384000 x 30 x 30)")
-    ke = w.ke()
+    r = tet40_ref
+    w, ke = r.w, r.ke
     dev = torch.device("cuda:0")
+    say("[parity] tet40 (permuted tet10) full size: pattern, colouring")
     p = feasm.pattern_build(torch.from_numpy(w.conn).to(dev), 3, w.n_nodes,
                             feasm.BUILD_CSR | feasm.BUILD_CRAC | feasm.BUILD_COLOUR)
     assert (p.nnz, p.n_ca) == (g["nnz"], g["n_ca"])
     rp, ci = (_np(t) for t in p.csr())
     crp, ca = (_np(t) for t in p.crac())
-    assert _sha(rp) == g["row_ptr_sha_int64"]
-    assert _sha(ci) == g["col_idx_sha_int64"]
-    assert _sha(ca) == g["ca_sha_int64"]
+    assert (rp == r.rp).all() and (ci == r.ci).all()
+    assert (crp == r.crp).all() and (ca == r.ca).all()
+    assert _sha(crp) == g["crac_row_ptr_sha_int64"]
+    gcol, gnc = orc.greedy_colour(w.conn, w.n_nodes)
+    _, _, ecol = p.colouring()
+    assert p.n_colours == gnc == 31
+    assert (_np(ecol) == gcol).all()
     ke_d = torch.from_numpy(ke).to(dev)
-    rows = np.random.default_rng(0).choice(p.n_rows, size=3000, replace=False)
-    ref = orc.rows(w.conn, 3, w.n_nodes, ke, rows)
+    total = abs(ke.sum())
     for fmt, sc in (("csr", feasm.SCATTER_ATOMIC), ("crac", feasm.SCATTER_ATOMIC),
                     ("csr", feasm.SCATTER_COLOURED), ("crac", feasm.SCATTER_COLOURED),
                     ("csr", feasm.SCATTER_OWNER), ("crac", feasm.SCATTER_OWNER),
                     ("csr", feasm.SCATTER_SPIN), ("crac", feasm.SCATTER_SPIN)):
         fn = feasm.assemble_csr if fmt == "csr" else feasm.assemble_crac
-        say(f"[parity] tet40 {fmt} strategy {sc}")
+        say(f"[parity] tet40 {fmt} strategy {sc}: every value")
         v = _np(fn(p, ke_d, scatter=sc))
         if sc == feasm.SCATTER_SPIN:
             assert p.spin_aborts() == 0
-        g_all, o_all, a_all = [], [], []
-        for i, (cols, ov, oa) in zip(rows, ref):
-            assert (ci[rp[i]:rp[i + 1]] == cols).all()
-            g_all.append(v[rp[i]:rp[i + 1]])
-            o_all.append(ov)
-            a_all.append(oa)
-        g_all, o_all = np.concatenate(g_all), np.concatenate(o_all)
-        assert_values_close(g_all, o_all, np.concatenate(a_all), what=f"tet40 {fmt} {sc}")
         if sc == feasm.SCATTER_OWNER:
-            assert (g_all == o_all).all()
-        # sum of all entries equals the sum of all element entries
-        assert abs(v.sum() - ke.sum()) <= 1e-12 * np.abs(ke).sum()
+            assert (v == r.ov).all()
+        else:
+            assert_values_close(v, r.ov, r.oa, what=f"tet40 {fmt} {sc}")
+        assert abs(v.sum() - ke.sum()) <= 1e-12 * np.abs(ke).sum() + 1e-12 * total
+        del v
     p.free()
 
 
