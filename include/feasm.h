@@ -334,6 +334,39 @@ int assemble_hex8(const feasm_pattern* p, int fmt, const double* coords, const d
  */
 int spin_aborts(feasm_pattern* p, int64_t* count);
 
+/*
+ * assemble_spin_noalloc -- FEASM_SCATTER_SPIN (assemble_csr / assemble_crac
+ * with row locks) for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  It allocates nothing: the lock words sit in a static device
+ * array of the library (2^21 int32, 8 MiB, held by each GPU the library
+ * runs on until the process ends), and the give-up count goes to the
+ * caller's `aborts`.
+ *   p        handle from pattern_build with the format `fmt`, built on the
+ *            current device; at most 2^21 rows (n_rows), element rows of
+ *            at most 32 entries
+ *   fmt      FEASM_FMT_CSR or FEASM_FMT_CRAC (position lookup as in
+ *            assemble_csr / assemble_crac)
+ *   ke       dev double [n_elem][n][n], as for assemble_csr
+ *   values   dev double [nnz]; overwritten with sum_e scatter(K_e), or added
+ *            to with flags = FEASM_ACCUMULATE
+ *   aborts   dev int32 [1], caller-owned: the kernel adds the number of
+ *            lanes that reached the spin limit (their rows are missing);
+ *            the caller zeroes it and reads it after the stream completes
+ *   flags    0 or FEASM_ACCUMULATE
+ * Same values as assemble_<fmt>(p, ke, values, FEASM_SCATTER_SPIN [|
+ * FEASM_ACCUMULATE], stream) up to summation order.  Each call first
+ * clears the lock words of the handle's rows and (flags = 0) the values,
+ * with kernels (no memset nodes), then launches the row-lock scatter;
+ * asynchronous.  Every call on one GPU shares the one lock array, so calls
+ * that overlap on a GPU (other streams, other threads) race and must be
+ * serialised by the caller.  Errors: EINVAL (null argument, unknown fmt or
+ * flag, a format the handle lacks, the handle's device not current);
+ * ELIMIT (more than 2^21 rows, element rows longer than 32); EHIP.
+ */
+int assemble_spin_noalloc(const feasm_pattern* p, int fmt, const double* ke, double* values,
+                          int32_t* aborts, int flags, hipStream_t stream);
+
 /* Releases the handle and its device arrays (synchronises the device). NULL is ignored. */
 void pattern_free(feasm_pattern* p);
 

@@ -73,6 +73,7 @@ SIGNATURES = {
     "last_error": (ctypes.c_char_p, []),
     "set_allocator": (INT, [ALLOC_FN, RELEASE_FN, P]),
     "spin_aborts": (INT, [P, PI64]),
+    "assemble_spin_noalloc": (INT, [P, INT, P, P, P, INT, P]),
 }
 
 _lib = None

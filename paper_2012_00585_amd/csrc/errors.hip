@@ -28,6 +28,8 @@ void set_error_for(const char* who, const char* what) noexcept {
     }
 }
 
+void set_error_literal(const char* msg) noexcept { g_fallback = msg; }
+
 }  // namespace feasm
 
 extern "C" const char* last_error(void) {

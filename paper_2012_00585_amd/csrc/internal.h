@@ -17,6 +17,8 @@ namespace feasm {
 void set_error(const std::string& msg) noexcept;
 // "who: what", without allocating when that fails.
 void set_error_for(const char* who, const char* what) noexcept;
+// A message with static storage duration, recorded without allocating.
+void set_error_literal(const char* msg) noexcept;
 
 // Runs the body of a C entry point.  The library's own code reports errors
 // by status; the only exceptions that can reach here come from the standard

@@ -154,6 +154,39 @@ __global__ void k_fill_zero_i32(int32_t* __restrict__ p, int64_t n) {
         p[i] = 0;
 }
 
+SpinArgs spin_args(const feasm_pattern* p, const double* ke, double* values, int32_t* locks,
+                   int32_t* aborts) {
+    SpinArgs A{};
+    A.conn = p->conn;
+    A.row_ptr = p->row_ptr;
+    A.col_idx = p->col_idx;
+    A.crac_row_ptr = p->crac_row_ptr;
+    A.ca = p->ca;
+    A.ke = ke;
+    A.values = values;
+    A.locks = locks;
+    A.aborts = aborts;
+    A.n_elem = p->n_elem;
+    A.k = p->k;
+    A.d = p->d;
+    A.n = p->n;
+    A.spin_limit = p->tune_spin_limit > 0    ? p->tune_spin_limit
+                   : p->tune_spin_limit < 0 ? 0
+                                            : ((int64_t)1 << 20);
+    return A;
+}
+
+hipError_t launch_spin_kernel(const feasm_pattern* p, int fmt, const SpinArgs& A, hipStream_t s) {
+    const unsigned blocks = (unsigned)ceil_div(p->n_elem * p->n, 256);
+    if (fmt == kCSR)
+        p->has_repeats ? k_spin<kCSR, true><<<blocks, 256, 0, s>>>(A)
+                       : k_spin<kCSR, false><<<blocks, 256, 0, s>>>(A);
+    else
+        p->has_repeats ? k_spin<kCRAC, true><<<blocks, 256, 0, s>>>(A)
+                       : k_spin<kCRAC, false><<<blocks, 256, 0, s>>>(A);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 int launch_spin(const feasm_pattern* pc, int fmt, const double* ke, double* values, hipStream_t s) {
@@ -170,31 +203,8 @@ int launch_spin(const feasm_pattern* pc, int fmt, const double* ke, double* valu
         k_fill_zero_i32<<<1, 64, 0, s>>>(p->spin_aborts, 1);
         FEASM_HIP(hipGetLastError());
     }
-    SpinArgs A{};
-    A.conn = p->conn;
-    A.row_ptr = p->row_ptr;
-    A.col_idx = p->col_idx;
-    A.crac_row_ptr = p->crac_row_ptr;
-    A.ca = p->ca;
-    A.ke = ke;
-    A.values = values;
-    A.locks = p->row_locks;
-    A.aborts = p->spin_aborts;
-    A.n_elem = p->n_elem;
-    A.k = p->k;
-    A.d = p->d;
-    A.n = p->n;
-    A.spin_limit = p->tune_spin_limit > 0    ? p->tune_spin_limit
-                   : p->tune_spin_limit < 0 ? 0
-                                            : ((int64_t)1 << 20);
-    const unsigned blocks = (unsigned)ceil_div(p->n_elem * p->n, 256);
-    if (fmt == kCSR)
-        p->has_repeats ? k_spin<kCSR, true><<<blocks, 256, 0, s>>>(A)
-                       : k_spin<kCSR, false><<<blocks, 256, 0, s>>>(A);
-    else
-        p->has_repeats ? k_spin<kCRAC, true><<<blocks, 256, 0, s>>>(A)
-                       : k_spin<kCRAC, false><<<blocks, 256, 0, s>>>(A);
-    FEASM_HIP(hipGetLastError());
+    const SpinArgs A = spin_args(p, ke, values, p->row_locks, p->spin_aborts);
+    FEASM_HIP(launch_spin_kernel(p, fmt, A, s));
     return FEASM_OK;
 }
 
@@ -215,6 +225,106 @@ extern "C" int spin_aborts(feasm_pattern* p, int64_t* count) {
         if (v > 0) {
             set_error_for("spin_aborts", "row-lock lanes reached the spin limit; results incomplete");
             return FEASM_EINCOMPLETE;
+        }
+        return FEASM_OK;
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free row-lock scatter.  The lock words live in `scratch`, a
+// device array of static storage that each GPU holds from module load until
+// the process ends (zero at load).  In host code `scratch` only names the
+// symbol: its device address is looked up once per device, with that device
+// current, and every kernel argument uses the address looked up.
+namespace feasm {
+namespace {
+
+constexpr int64_t kNoAllocMaxRows = int64_t(1) << 21;  // 8 MiB of lock words
+constexpr int kMaxDevices = 64;
+
+__device__ __align__(256) int32_t scratch[kNoAllocMaxRows];
+
+std::mutex g_scratch_mu;
+int32_t* g_scratch_dev[kMaxDevices] = {};
+
+__global__ void k_zero_values(double* __restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+// The current device's address of `scratch` (looked up on its first use).
+int scratch_address(int device, int32_t** out) {
+    std::lock_guard<std::mutex> guard(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            set_error_literal("assemble_spin_noalloc: hipGetSymbolAddress of the lock words failed");
+            return FEASM_EHIP;
+        }
+        g_scratch_dev[device] = static_cast<int32_t*>(ptr);
+    }
+    *out = g_scratch_dev[device];
+    return FEASM_OK;
+}
+
+}  // namespace
+}  // namespace feasm
+
+extern "C" int assemble_spin_noalloc(const feasm_pattern* p, int fmt, const double* ke,
+                                     double* values, int32_t* aborts, int flags,
+                                     hipStream_t stream) {
+    return feasm::guarded("assemble_spin_noalloc", [&]() -> int {
+        using namespace feasm;
+        if (!p || !ke || !values || !aborts) {
+            set_error_literal("assemble_spin_noalloc: null handle or buffer");
+            return FEASM_EINVAL;
+        }
+        if (fmt != FEASM_FMT_CSR && fmt != FEASM_FMT_CRAC) {
+            set_error_literal("assemble_spin_noalloc: fmt must be FEASM_FMT_CSR or FEASM_FMT_CRAC");
+            return FEASM_EINVAL;
+        }
+        if ((fmt == FEASM_FMT_CSR && !(p->flags & FEASM_BUILD_CSR)) ||
+            (fmt == FEASM_FMT_CRAC && !(p->flags & FEASM_BUILD_CRAC))) {
+            set_error_literal("assemble_spin_noalloc: handle was built without this format");
+            return FEASM_EINVAL;
+        }
+        if (flags != 0 && flags != FEASM_ACCUMULATE) {
+            set_error_literal("assemble_spin_noalloc: flags must be 0 or FEASM_ACCUMULATE");
+            return FEASM_EINVAL;
+        }
+        if (p->n > kSpinMaxN) {
+            set_error_literal("assemble_spin_noalloc: element matrices up to 32 x 32 only");
+            return FEASM_ELIMIT;
+        }
+        if (p->n_rows > kNoAllocMaxRows) {
+            set_error_literal("assemble_spin_noalloc: more than 2^21 rows (the static lock array)");
+            return FEASM_ELIMIT;
+        }
+        int device = -1;
+        if (hipGetDevice(&device) != hipSuccess || device != p->device) {
+            set_error_literal("assemble_spin_noalloc: the handle's device must be current");
+            return FEASM_EINVAL;
+        }
+        if (device < 0 || device >= kMaxDevices) {
+            set_error_literal("assemble_spin_noalloc: device index beyond 63");
+            return FEASM_ELIMIT;
+        }
+        int32_t* locks = nullptr;
+        const int rc = scratch_address(device, &locks);
+        if (rc != FEASM_OK) return rc;
+        // every lock word this launch can take starts free, whatever earlier
+        // calls left; the reset is a kernel, so the call can be captured
+        const unsigned g = (unsigned)std::min<int64_t>(ceil_div(p->n_rows, 256), 4096);
+        k_fill_zero_i32<<<g, 256, 0, stream>>>(locks, p->n_rows);
+        if (flags == 0) {
+            const unsigned gv = (unsigned)std::min<int64_t>(ceil_div(p->nnz, 256), 16384);
+            k_zero_values<<<gv, 256, 0, stream>>>(values, p->nnz);
+        }
+        const SpinArgs A = spin_args(p, ke, values, locks, aborts);
+        if (launch_spin_kernel(p, fmt, A, stream) != hipSuccess) {
+            set_error_literal("assemble_spin_noalloc: kernel launch failed");
+            return FEASM_EHIP;
         }
         return FEASM_OK;
     });

@@ -71,6 +71,8 @@ int main() {
            "null handle");
     int64_t count = 0;
     expect(spin_aborts(nullptr, &count), FEASM_EINVAL, "spin_aborts", nullptr);
+    expect(assemble_spin_noalloc(nullptr, FEASM_FMT_CSR, dptr, dptr, nullptr, 0, nullptr),
+           FEASM_EINVAL, "assemble_spin_noalloc", "null handle");
 
     expect(generate_ke(0, 4, 4, 1, 0, nullptr, nullptr), FEASM_EINVAL, "generate_ke null", nullptr);
     expect(generate_ke(2, 4, 4, 1, 0, dptr, nullptr), FEASM_EINVAL, "generate_ke recipe", nullptr);
