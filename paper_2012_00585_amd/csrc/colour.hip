@@ -7,7 +7,7 @@
 // shares a node with it.  That colour depends only on the colours of e's
 // smaller neighbours, so e can be coloured as soon as all of them are, and
 // the elements coloured at one time share no node.  The device runs the
-// greedy order as rounds over a frontier:
+// greedy order as rounds over a frontier (a wavefront per element):
 //   * pred[e] counts the (element, shared node) incidences of e with smaller
 //     elements (a neighbour sharing two nodes counts twice);
 //   * the first frontier holds the elements with pred 0;
@@ -51,31 +51,41 @@ __global__ void k_pred_count(const int32_t* __restrict__ conn, int32_t k, int64_
     }
 }
 
-// One greedy round.  counts[r % 3] holds this round's frontier size; the
-// next frontier is counted in counts[(r + 1) % 3]; counts[(r + 2) % 3] (read
-// by the previous round) is cleared for the round after next.
-__global__ void k_greedy_round(const int32_t* __restrict__ conn, int32_t k,
-                               const int64_t* __restrict__ inc_ptr,
-                               const int32_t* __restrict__ inc_elem, int32_t* __restrict__ colour,
-                               int32_t* __restrict__ pred, const int32_t* __restrict__ front_in,
-                               int32_t* __restrict__ front_out, int32_t* __restrict__ counts,
-                               int32_t round, int32_t* __restrict__ max_colour,
-                               unsigned long long* __restrict__ n_coloured) {
+__device__ inline uint64_t wave_or(uint64_t v) {
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+    return v;
+}
+
+// One greedy round, one wavefront per frontier element (its lanes take the
+// element's nodes and walk their incidence lists).  counts[r % 3] holds this
+// round's frontier size; the next frontier is counted in counts[(r + 1) % 3];
+// counts[(r + 2) % 3] (read by the previous round) is cleared for the round
+// after next.  All lanes of a wavefront take the same element, so the
+// shuffles always see the whole wavefront.
+__global__ void __launch_bounds__(256)
+    k_greedy_round(const int32_t* __restrict__ conn, int32_t k,
+                   const int64_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc_elem,
+                   int32_t* __restrict__ colour, int32_t* __restrict__ pred,
+                   const int32_t* __restrict__ front_in, int32_t* __restrict__ front_out,
+                   int32_t* __restrict__ counts, int32_t round, int32_t* __restrict__ max_colour,
+                   unsigned long long* __restrict__ n_coloured) {
     const int32_t cur = round % 3, nxt = (round + 1) % 3, clr = (round + 2) % 3;
     const int32_t n = counts[cur];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         counts[clr] = 0;
         if (n > 0) atomicAdd(n_coloured, (unsigned long long)n);
     }
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int64_t w0 = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    for (int64_t i = w0; i < n; i += waves) {
         const int32_t e = front_in[i];
         const int32_t* ce = conn + (int64_t)e * k;
         // smallest colour unused by the smaller neighbours, 64 colours at a time
         int32_t chosen = -1;
         for (int32_t base = 0; chosen < 0; base += 64) {
             uint64_t used = 0;
-            for (int32_t a = 0; a < k; ++a) {
+            for (int32_t a = lane; a < k; a += 64) {
                 const int32_t v = ce[a];
                 for (int64_t t = inc_ptr[v]; t < inc_ptr[v + 1]; ++t) {
                     const int32_t f = inc_elem[t];
@@ -84,12 +94,15 @@ __global__ void k_greedy_round(const int32_t* __restrict__ conn, int32_t k,
                     if (c >= 0 && c < 64) used |= 1ull << c;
                 }
             }
+            used = wave_or(used);
             if (~used) chosen = base + __ffsll((unsigned long long)~used) - 1;
         }
-        colour[e] = chosen;
-        atomicMax(max_colour, chosen);
+        if (lane == 0) {
+            colour[e] = chosen;
+            atomicMax(max_colour, chosen);
+        }
         // release the larger neighbours, once per shared node
-        for (int32_t a = 0; a < k; ++a) {
+        for (int32_t a = lane; a < k; a += 64) {
             const int32_t v = ce[a];
             for (int64_t t = inc_ptr[v]; t < inc_ptr[v + 1]; ++t) {
                 const int32_t f = inc_elem[t];
@@ -195,7 +208,7 @@ int build_colouring(feasm_pattern* p, hipStream_t s) {
     // the longest chain of neighbours in increasing element order bounds the
     // rounds (a few hundred on the structured meshes); check every kBatch
     constexpr int kBatch = 32;
-    const unsigned g = std::min(grid(E, 256), 2048u);
+    const unsigned g = std::min(grid(E * 64, 256), 2048u);  // a wavefront per element
     int64_t round = 0;
     for (;;) {
         for (int r = 0; r < kBatch; ++r, ++round) {
