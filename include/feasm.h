@@ -450,24 +450,56 @@ int set_allocator(feasm_alloc_fn alloc, feasm_release_fn release, void* ctx);
 
 /*
  * Serving engine: requests for one assembly followed by n_reassembly
- * value-only re-assemblies of a registered mesh (whose pattern stays
- * resident), each iteration with fresh element matrices from generate_ke
- * (recipe of the mesh, key seed*1000003 + iteration*7919 + 1 mod 2^64).
+ * value-only re-assemblies of a mesh, continuously batched.
+ *
+ * Meshes (host array [n_meshes] of feasm_serve_mesh): the connectivity and
+ * sizes as for pattern_build (conn: dev int32 [n_elem][nodes_per_elem],
+ * kept alive by the caller for the call), and either
+ *   - pattern: a resident handle of the caller (never freed by the engine;
+ *     its re-assembly state is built before the clock starts), or
+ *   - pattern = NULL: the engine builds the pattern with pattern_build on the
+ *     first request that needs it (a miss; the loop stalls for the build and
+ *     the first re-assembly's record) and keeps it in a cache of at most
+ *     config->pattern_cache_bytes bytes of pattern arrays (<= 0: unbounded),
+ *     evicting the least recently used patterns no admitted request uses; it
+ *     frees them at the end.
+ * Element matrices of iteration i of a request with key s: with ke_pool ==
+ * NULL, fresh ones from generate_ke(recipe, ..., key s*1000003 + i*7919 + 1
+ * mod 2^64) on a side stream into the slot's ping-pong buffers; otherwise
+ * block (s + i) mod pool_size of ke_pool (dev double [pool_size][n_elem][n][n],
+ * pre-generated by the caller), read in place.
+ *
  * Continuous batching: arriving requests are admitted FIFO into free slots
- * (each with its own streams and buffers) whenever the sum of admitted
- * footprints (2 element-matrix buffers + values) stays within hbm_budget
- * (<= 0: no limit; a request is always admitted when nothing else runs);
- * every slot issues its next iteration as soon as the previous completes,
- * so admitted requests overlap on the device.  Runs until every request is
- * done; times are host seconds since the call started.  Slot buffers are
- * allocated once, for the largest mesh, and each mesh's re-assembly lookup
- * state is built before the clock starts.  Synchronous; uses AUTO strategy.
- *   meshes/recipes  host arrays [n_meshes]: handles, generate_ke recipes
- *   requests        host array [n_requests], sorted by arrival_s
- *   results         host array [n_requests]
- *   reassembly_latency  optional host array [sum of n_reassembly]: each
- *                   re-assembly's issue-to-completion time, request order
+ * (each with its own streams) whenever the sum of admitted footprints (the
+ * two generator buffers unless the mesh has a pool, plus the values; for a
+ * pattern not yet built the values are bounded by n_elem*n*n) stays within
+ * config->hbm_budget (<= 0: no limit; a request is always admitted when
+ * nothing else runs); every slot issues its next iteration as soon as the
+ * previous completes, so admitted requests overlap on the device.  The
+ * strategy is each handle's AUTO choice.  Synchronous; runs until every
+ * request is done.
+ *
+ * Times (seconds since the start of the run): admitted_s is host time;
+ * assembled_s and done_s are the device completion times of the assembly
+ * and of the request (timing events, relative to an event recorded at the
+ * start); reassembly_latency (optional host array [sum of n_reassembly],
+ * request order) holds each re-assembly's device time from its issue on the
+ * slot's stream to its completion.  stats (optional) receives pattern cache
+ * counts, the host time spent building patterns on misses, and the summed
+ * device times of the generator kernels and of the assemblies.
  */
+typedef struct {
+    const int32_t* conn;  /* dev [n_elem][nodes_per_elem] (may be NULL when pattern is given) */
+    int64_t n_elem;
+    int32_t nodes_per_elem;
+    int32_t dofs_per_node;
+    int64_t n_nodes;
+    int32_t recipe;                 /* generate_ke recipe (0 or 1) when ke_pool is NULL */
+    int32_t pool_size;              /* blocks in ke_pool */
+    const double* ke_pool;          /* optional dev [pool_size][n_elem][n][n] */
+    const feasm_pattern* pattern;   /* optional resident handle of the caller */
+} feasm_serve_mesh;
+
 typedef struct {
     double arrival_s;     /* seconds after the start of the run */
     int32_t mesh;         /* index into the mesh table */
@@ -480,9 +512,25 @@ typedef struct {
     double admitted_s, assembled_s, done_s;
 } feasm_request_result;
 
-int serve_run(const feasm_pattern* const* meshes, const int32_t* recipes, int64_t n_meshes,
-              const feasm_request* requests, int64_t n_requests, int fmt, int32_t slots,
-              int64_t hbm_budget, feasm_request_result* results, double* reassembly_latency);
+typedef struct {
+    int32_t fmt;                  /* FEASM_FMT_CSR or FEASM_FMT_CRAC */
+    int32_t slots;                /* 1 .. 256; 1 = one request at a time (FIFO) */
+    int64_t hbm_budget;           /* admission budget in bytes (<= 0: none) */
+    int64_t pattern_cache_bytes;  /* engine-built patterns kept (<= 0: no limit) */
+} feasm_serve_config;
+
+typedef struct {
+    int64_t pattern_hits, pattern_misses, pattern_evictions;
+    int64_t pattern_cache_peak_bytes, patterns_resident_at_end;
+    double pattern_build_s;   /* host seconds in pattern_build + first record on misses */
+    double generate_ms;       /* device time of the generator kernels */
+    double assemble_ms;       /* device time of the assemblies and re-assemblies */
+    int64_t generated_bytes;  /* element-matrix bytes generated */
+} feasm_serve_stats;
+
+int serve_run(const feasm_serve_mesh* meshes, int64_t n_meshes, const feasm_request* requests,
+              int64_t n_requests, const feasm_serve_config* config, feasm_request_result* results,
+              double* reassembly_latency, feasm_serve_stats* stats);
 
 #ifdef __cplusplus
 }

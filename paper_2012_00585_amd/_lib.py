@@ -34,6 +34,14 @@ PP = ctypes.POINTER(ctypes.c_void_p)
 PI64 = ctypes.POINTER(ctypes.c_int64)
 PI32 = ctypes.POINTER(ctypes.c_int32)
 
+class ServeMesh(ctypes.Structure):
+    _fields_ = [("conn", ctypes.c_void_p), ("n_elem", ctypes.c_int64),
+                ("nodes_per_elem", ctypes.c_int32), ("dofs_per_node", ctypes.c_int32),
+                ("n_nodes", ctypes.c_int64), ("recipe", ctypes.c_int32),
+                ("pool_size", ctypes.c_int32), ("ke_pool", ctypes.c_void_p),
+                ("pattern", ctypes.c_void_p)]
+
+
 class Request(ctypes.Structure):
     _fields_ = [("arrival_s", ctypes.c_double), ("mesh", ctypes.c_int32),
                 ("n_reassembly", ctypes.c_int32), ("seed", ctypes.c_uint64),
@@ -43,6 +51,19 @@ class Request(ctypes.Structure):
 class RequestResult(ctypes.Structure):
     _fields_ = [("admitted_s", ctypes.c_double), ("assembled_s", ctypes.c_double),
                 ("done_s", ctypes.c_double)]
+
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("fmt", ctypes.c_int32), ("slots", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_int64), ("pattern_cache_bytes", ctypes.c_int64)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("pattern_hits", ctypes.c_int64), ("pattern_misses", ctypes.c_int64),
+                ("pattern_evictions", ctypes.c_int64), ("pattern_cache_peak_bytes", ctypes.c_int64),
+                ("patterns_resident_at_end", ctypes.c_int64), ("pattern_build_s", ctypes.c_double),
+                ("generate_ms", ctypes.c_double), ("assemble_ms", ctypes.c_double),
+                ("generated_bytes", ctypes.c_int64)]
 
 
 # set_allocator callbacks: alloc(bytes, stream, ctx) -> ptr, release(ptr, stream, ctx)
@@ -68,8 +89,9 @@ SIGNATURES = {
     "assemble_batch": (INT, [P, P, P, P]),
     "batch_info": (INT, [P, PI32, PI64, PI64, P]),
     "batch_free": (None, [P]),
-    "serve_run": (INT, [P, P, I64, ctypes.POINTER(Request), I64, INT, I32, I64,
-                        ctypes.POINTER(RequestResult), P]),
+    "serve_run": (INT, [ctypes.POINTER(ServeMesh), I64, ctypes.POINTER(Request), I64,
+                        ctypes.POINTER(ServeConfig), ctypes.POINTER(RequestResult), P,
+                        ctypes.POINTER(ServeStats)]),
     "last_error": (ctypes.c_char_p, []),
     "set_allocator": (INT, [ALLOC_FN, RELEASE_FN, P]),
     "spin_aborts": (INT, [P, PI64]),

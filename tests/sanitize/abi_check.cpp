@@ -86,8 +86,29 @@ int main() {
            nullptr);
     expect(batch_info(nullptr, nullptr, nullptr, nullptr, nullptr), FEASM_EINVAL, "batch_info",
            nullptr);
-    expect(serve_run(nullptr, nullptr, 0, nullptr, 0, 0, 1, 0, nullptr, nullptr), FEASM_EINVAL,
+    expect(serve_run(nullptr, 0, nullptr, 0, nullptr, nullptr, nullptr, nullptr), FEASM_EINVAL,
            "serve_run", nullptr);
+    {
+        feasm_serve_mesh mesh{};
+        mesh.conn = conn;
+        mesh.n_elem = 4;
+        mesh.nodes_per_elem = 4;
+        mesh.dofs_per_node = 1;
+        mesh.n_nodes = 9;
+        feasm_serve_config cfg{};
+        cfg.fmt = FEASM_FMT_CRAC;
+        cfg.slots = 0;
+        expect(serve_run(&mesh, 1, nullptr, 0, &cfg, nullptr, nullptr, nullptr), FEASM_EINVAL,
+               "serve_run slots", "slots");
+        cfg.slots = 2;
+        mesh.recipe = 5;
+        expect(serve_run(&mesh, 1, nullptr, 0, &cfg, nullptr, nullptr, nullptr), FEASM_EINVAL,
+               "serve_run recipe", "recipe");
+        mesh.recipe = 0;
+        mesh.conn = nullptr;
+        expect(serve_run(&mesh, 1, nullptr, 0, &cfg, nullptr, nullptr, nullptr), FEASM_EINVAL,
+               "serve_run no mesh", "connectivity");
+    }
 
     expect(set_allocator(fake_alloc, nullptr, nullptr), FEASM_EINVAL, "set_allocator half",
            "both");
