@@ -67,7 +67,8 @@ enum feasm_status {
 enum {
     FEASM_BUILD_CSR = 1,    /* row_ptr[n_rows+1], col_idx[nnz] */
     FEASM_BUILD_CRAC = 2,   /* crac_row_ptr[n_rows+1], col_align[n_ca] */
-    FEASM_BUILD_COLOUR = 4  /* element colouring for the atomic-free scatter */
+    FEASM_BUILD_COLOUR = 4, /* element colouring for the atomic-free scatter */
+    FEASM_BUILD_TILES = 8   /* element tiles for the atomic scatter (see FEASM_SCATTER_ATOMIC) */
 };
 
 /* format selector for reassemble_values */
@@ -76,7 +77,13 @@ enum { FEASM_FMT_CSR = 0, FEASM_FMT_CRAC = 1 };
 /* scatter strategy of the numeric calls */
 enum {
     FEASM_SCATTER_AUTO = 0,     /* the library's choice for this handle (row-owned) */
-    FEASM_SCATTER_ATOMIC = 1,   /* one hardware FP64 atomic add per contribution */
+    FEASM_SCATTER_ATOMIC = 1,   /* hardware FP64 atomic adds.  Without tiles: one atomic
+                                   per contribution.  With tiles (FEASM_BUILD_TILES): a
+                                   workgroup sums the contributions of a tile of nearby
+                                   elements per distinct (row, column) in LDS, then writes
+                                   each sum once -- a plain store where the tile holds
+                                   every element coupling the two nodes, one atomic add
+                                   otherwise */
     FEASM_SCATTER_COLOURED = 2, /* one launch per colour, plain read-modify-write */
     FEASM_SCATTER_OWNER = 3,    /* row-owned: each node row is summed by one wavefront
                                    from the incident elements, in element order, and
@@ -116,7 +123,16 @@ enum {
  *
  * Colouring (Section 3.3): elements sharing a node get different colours;
  * the element list is grouped by colour, increasing element id within a
- * colour.
+ * colour.  The colouring is the greedy one in element order: each element
+ * takes the smallest colour unused by the smaller elements it shares a node
+ * with.
+ *
+ * Tiles (FEASM_BUILD_TILES): elements grouped into small sets of
+ * neighbouring elements (aggregates around a distance-2 independent set of
+ * the element graph, cut into tiles of a few dozen elements) with each
+ * tile's distinct node pairs, for the atomic scatter.  Any element order
+ * and mesh is accepted; elements whose tile has more distinct node pairs
+ * than the accumulator holds fall back to one atomic per contribution.
  *
  * Errors: EINVAL for bad arguments; ERANGE if a node id is out of range
  * (checked on the device, reported before returning); EOVERFLOW for int32
@@ -237,6 +253,10 @@ int pattern_colouring(const feasm_pattern* p, const int64_t** colour_ptr,
  *                                   n in [1, 16] = the pipelined grid with n
  *                                   blocks per compute unit; -1 = every node
  *                                   one per wavefront
+ *   FEASM_TUNE_TILE_CAP             handles with tiles: elements per tile at
+ *                                   most, 1 to 64 (0: chosen from the element
+ *                                   size); rebuilds the tiles (synchronises
+ *                                   the device)
  *   FEASM_TUNE_SPIN_LIMIT           FEASM_SCATTER_SPIN: lock acquire attempts
  *                                   per lane before it gives up (0: 2^20;
  *                                   -1: none, every lane gives up at once,
@@ -253,7 +273,8 @@ enum {
     FEASM_TUNE_OWNER_PREFETCH = 7,
     FEASM_TUNE_SPMV_CHUNK = 8,
     FEASM_TUNE_HEX8_PIPE = 9,
-    FEASM_TUNE_SPIN_LIMIT = 10
+    FEASM_TUNE_SPIN_LIMIT = 10,
+    FEASM_TUNE_TILE_CAP = 11
 };
 int pattern_tune(feasm_pattern* p, int key, int64_t value);
 

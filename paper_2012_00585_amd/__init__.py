@@ -23,6 +23,7 @@ from ._lib import FeasmError
 BUILD_CSR = 1
 BUILD_CRAC = 2
 BUILD_COLOUR = 4
+BUILD_TILES = 8
 FMT_CSR = 0
 FMT_CRAC = 1
 SCATTER_AUTO = 0
@@ -42,6 +43,7 @@ TUNE_OWNER_PREFETCH = 7
 TUNE_SPMV_CHUNK = 8
 TUNE_HEX8_PIPE = 9
 TUNE_SPIN_LIMIT = 10
+TUNE_TILE_CAP = 11
 
 _HIP_D2D = 3  # hipMemcpyDeviceToDevice
 

@@ -426,6 +426,15 @@ int assemble_impl(const feasm_pattern* p, int fmt, const double* ke, double* val
         FEASM_HIP(hipGetLastError());
     }
     if (scatter == FEASM_SCATTER_ATOMIC) {
+        if (p->n_tiles > 0 && !cache && !cache_out) {
+            // tiles: LDS sums per distinct (row, column), one write each;
+            // elements of tiles beyond the accumulator one atomic per entry
+            const int rc = launch_tiled_atomic(p, fmt, ke, values, accumulate, s);
+            if (rc != FEASM_OK || p->n_tile_direct == 0) return rc;
+            A.elem_list = p->tile_direct;
+            A.count = p->n_tile_direct;
+            return launch(fmt, true, A, sh, s);
+        }
         A.elem_list = nullptr;
         A.count = p->n_elem;
         return launch(fmt, true, A, sh, s);
@@ -525,6 +534,10 @@ extern "C" int reassemble_values(feasm_pattern* p, int fmt, const double* ke, do
             return assemble_impl(p, fmt, ke, values, scatter, nullptr, nullptr, stream,
                                  "reassemble_values", p->owner_map);
         }
+        if (strategy == FEASM_SCATTER_ATOMIC && p->n_tiles > 0)
+            // the tiles' lookups are one per distinct node pair: nothing to record
+            return assemble_impl(p, fmt, ke, values, scatter, nullptr, nullptr, stream,
+                                 "reassemble_values");
         if (p->cache && p->cache->valid && p->cache->fmt == fmt)
             return assemble_impl(p, fmt, ke, values, scatter, p->cache->base, nullptr, stream,
                                  "reassemble_values");
@@ -565,6 +578,18 @@ extern "C" int pattern_tune(feasm_pattern* p, int key, int64_t value) {
                 FEASM_FAIL(FEASM_EINVAL, "pattern_tune: owner blocks per CU must be in [0, 64]");
             p->tune_owner_blocks_per_cu = (int32_t)value;
             return FEASM_OK;
+        }
+        if (key == FEASM_TUNE_TILE_CAP) {
+            if (value < 0 || value > 64)
+                FEASM_FAIL(FEASM_EINVAL, "pattern_tune: tile cap must be in [0, 64]");
+            if (!(p->flags & FEASM_BUILD_TILES))
+                FEASM_FAIL(FEASM_EINVAL, "pattern_tune: handle was built without FEASM_BUILD_TILES");
+            FEASM_HIP(hipDeviceSynchronize());  // queued calls may still read the tiles
+            feasm::release_tiles(p);
+            p->tune_tile_cap = (int32_t)value;
+            const int rc = feasm::build_tiles(p, nullptr);
+            if (rc != FEASM_OK) feasm::release_tiles(p);
+            return rc;
         }
         if (key == FEASM_TUNE_THREADS_PER_ELEM) {
             if (value != 0 && value != 16 && value != 32 && value != 64 && value != 128 && value != 256)

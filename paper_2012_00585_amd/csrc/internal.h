@@ -144,6 +144,24 @@ struct feasm_pattern {
     // first use (owner_map, cache, row_locks) between threads sharing a handle.
     mutable std::mutex lazy_mu;
 
+    // element tiles of the atomic scatter (FEASM_BUILD_TILES; tiles.hip)
+    int64_t n_tiles = 0;              // 0: none (the element-centric kernel serves)
+    int32_t tile_cap = 0;             // elements per tile at most
+    int32_t tile_max_pairs = 0;       // distinct node pairs the accumulator holds
+    int32_t tile_max_nodes = 0;       // local nodes of a tile at most
+    int32_t tile_max_stage_csr = 0;   // index ints a tile stages (CSR, CRAC) at most
+    int32_t tile_max_stage_crac = 0;
+    int32_t* tile_ptr = nullptr;      // dev [n_tiles+1]: tile t = tile_elems[tile_ptr[t], tile_ptr[t+1])
+    int32_t* tile_elems = nullptr;    // dev [n_elem]: element ids, tile by tile, ascending in a tile
+    int32_t* tile_meta = nullptr;     // dev [n_tiles][4]: distinct node pairs, local nodes,
+                                      //   staged CSR ints, staged CRAC ints
+    int32_t* tile_nodes = nullptr;    // dev [n_elem*k]: tile t's nodes at tile_ptr[t]*k, ascending
+    uint32_t* tile_pairs = nullptr;   // dev [n_elem*k*k]: at tile_ptr[t]*k*k, local a | local b << 11
+                                      //   | complete << 31, in (a, b) order
+    uint16_t* tile_slot = nullptr;    // dev [n_elem*k*k]: pair of entry (element i of the tile, a, b)
+    int32_t* tile_direct = nullptr;   // dev [n_tile_direct]: elements of tiles beyond the accumulator
+    int64_t n_tile_direct = 0;
+
     // tuning (0 = library default)
     int32_t tune_owner_blocks_per_cu = 0;  // >0: persistent row-owned grid of this size per CU
     int32_t tune_atomic_tpe = 0;           // threads per element of the atomic/coloured scatter
@@ -154,6 +172,7 @@ struct feasm_pattern {
     int32_t tune_owner_prefetch = 0;       // flat batches: issue the next batch early
     int32_t tune_spmv_chunk = 0;           // matrix-vector product: values per LDS chunk
     int64_t tune_spin_limit = 0;           // row-lock scatter: acquire attempts per lane
+    int32_t tune_tile_cap = 0;             // elements per atomic-scatter tile at most (0: by size)
     int32_t tune_hex8_pipe = 0;            // fused hexahedra: -1 one node per wavefront, 0 auto,
                                            // else pipelined blocks per CU
 };
@@ -174,6 +193,16 @@ int build_node_order(feasm_pattern* p, hipStream_t s, int64_t* n_light_host);
 
 // Colouring (colour.hip): fills p->elem_colour, colour_elems, colour_ptr, n_colours.
 int build_colouring(feasm_pattern* p, hipStream_t s);
+
+// Element tiles of the atomic scatter (tiles.hip): build_tiles fills the
+// tile arrays of the handle (or leaves n_tiles = 0 when tiles cannot be
+// formed) and synchronises s; launch_tiled_atomic runs the tiles whose pairs
+// fit the accumulator (the caller runs the element-centric kernel over
+// tile_direct).
+int build_tiles(feasm_pattern* p, hipStream_t s);
+int launch_tiled_atomic(const feasm_pattern* p, int fmt, const double* ke, double* values,
+                        bool accumulate, hipStream_t s);
+void release_tiles(feasm_pattern* p);
 
 // Row-lock scatter (spin.hip) of one mesh into reset (or accumulated) values.
 int launch_spin(const feasm_pattern* p, int fmt, const double* ke, double* values, hipStream_t s);

@@ -448,6 +448,7 @@ int build(feasm_pattern* p, const int32_t* conn_in, hipStream_t s) {
     TRY(build_node_order(p, s, &n_light));
 
     if (p->flags & FEASM_BUILD_COLOUR) TRY(build_colouring(p, s));
+    if (p->flags & FEASM_BUILD_TILES) TRY(build_tiles(p, s));
     FEASM_HIP(hipStreamSynchronize(s));
     p->n_light = n_light;
     return FEASM_OK;
@@ -464,6 +465,7 @@ void release_pattern(feasm_pattern* p) {
     for (void* a : arrs) dev_free(p->alloc, a, nullptr);
     release_cache(p);
     release_owner_map(p);
+    release_tiles(p);
 }
 
 }  // namespace feasm
@@ -479,7 +481,8 @@ extern "C" int pattern_build(const int32_t* conn, int64_t n_elem, int32_t nodes_
         if (n_elem <= 0 || nodes_per_elem <= 0 || dofs_per_node <= 0 || n_nodes <= 0)
             FEASM_FAIL(FEASM_EINVAL, "pattern_build: n_elem, nodes_per_elem, dofs_per_node and "
                                      "n_nodes must be positive");
-        if (build_flags & ~(uint32_t)(FEASM_BUILD_CSR | FEASM_BUILD_CRAC | FEASM_BUILD_COLOUR))
+        if (build_flags & ~(uint32_t)(FEASM_BUILD_CSR | FEASM_BUILD_CRAC | FEASM_BUILD_COLOUR |
+                                      FEASM_BUILD_TILES))
             FEASM_FAIL(FEASM_EINVAL, "pattern_build: unknown build flag");
         if (!(build_flags & (FEASM_BUILD_CSR | FEASM_BUILD_CRAC)))
             FEASM_FAIL(FEASM_EINVAL, "pattern_build: request FEASM_BUILD_CSR and/or FEASM_BUILD_CRAC");
