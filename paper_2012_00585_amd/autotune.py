@@ -7,6 +7,12 @@ candidate on the class's largest mesh with single-mesh calls -- row-owned
 element 16 ... 64) -- keeps the fastest and applies it to every handle of
 the class with ``Pattern.tune``.  Results do not depend on the choice; only
 time does.  Choices can be saved to and loaded from a JSON file.
+
+``autotune_batch`` then re-times, for every class, the leading single-mesh
+candidates inside the batched launch they configure (the batch runs its
+own kernels per path, whose speed need not follow the single-mesh ranking)
+and keeps, class by class, the candidate with the fastest whole-batch
+replay.
 """
 from __future__ import annotations
 
@@ -116,6 +122,50 @@ def autotune(patterns, kes, values, fmt, reps=5, warmup=2, max_tpe=64, log=None)
                 f"rep {patterns[rep].n_elem} elements): "
                 + ", ".join(f"{c.label()} {c.ms:.3f} ms" for c in ranked[:4]))
     return out
+
+
+def autotune_batch(patterns, kes, values, fmt, make_batch, reps=3, warmup=1, top=3, log=None):
+    """Tune for the batched launch: single-mesh ranking per class first, then,
+    class by class (largest work first), each of the class's ``top`` leading
+    candidates (and the row-owned one with one row per wavefront) applied to
+    the whole class and timed as a replay of ``make_batch(patterns)``; the
+    fastest replay's candidate stays.  Returns ({class: [Choice ranked by
+    batch time]}, batch time in ms of the final choice)."""
+    single = autotune(patterns, kes, values, fmt, reps=reps, warmup=warmup, max_tpe=64, log=log)
+    classes = {}
+    for i, p in enumerate(patterns):
+        classes.setdefault(size_class(p), []).append(i)
+    work = {c: sum(patterns[i].n_elem * patterns[i].n ** 2 for i in m) for c, m in classes.items()}
+
+    def batch_ms():
+        b = make_batch(patterns)
+        try:
+            return _time(lambda: b.assemble(kes, values), reps, warmup)
+        finally:
+            b.free()
+
+    out = {}
+    current = batch_ms()
+    for cls in sorted(classes, key=lambda c: -work[c]):
+        members = classes[cls]
+        tried = list(single[cls][:top])
+        if not any(c.strategy == SCATTER_OWNER and c.rows in (0, 1) for c in tried):
+            tried += [c for c in single[cls] if c.strategy == SCATTER_OWNER and c.rows in (0, 1)][:1]
+        timed = []
+        for c in tried:
+            for i in members:
+                apply(patterns[i], c)
+            t = batch_ms()
+            timed.append(Choice(c.strategy, c.tpe, c.rows, c.batch, t))
+        timed.sort(key=lambda c: c.ms)
+        for i in members:
+            apply(patterns[i], timed[0])
+        current = timed[0].ms
+        out[cls] = timed
+        if log:
+            log(f"[autotune] batch, class k={cls[0]} d={cls[1]} bucket={cls[2]}: "
+                + ", ".join(f"{c.label()} {c.ms:.3f} ms" for c in timed))
+    return out, current
 
 
 def save(choices, path):

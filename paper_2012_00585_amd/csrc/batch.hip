@@ -36,6 +36,8 @@ using namespace scatter;
 enum Path : int32_t {
     kOwnG4 = 0, kOwnG8, kOwnG16, kOwnG32, kOwnG64J1, kOwnG64J2, kOwnG64J4, kOwnG64J8, kOwnG64J16,
     kRows2J1, kRows2J2,
+    kPipe24,  // 8-node hexes, 3 DOFs per node, at most 8 incident entries per node:
+              // the single-mesh flat row-owned kernel, one node row per tile
     kElemA16, kElemA32, kElemA64, kElemP16, kElemP32, kElemP64,
     kNumPaths
 };
@@ -71,62 +73,94 @@ __global__ void __launch_bounds__(256)
     }
 }
 
+// Tiles of a path are split into kXcds contiguous ranges, one counter each.
+constexpr int kXcds = 8;
+
 __global__ void k_batch_reset(unsigned long long* counters, int32_t n) {
-    if ((int)threadIdx.x < n) counters[threadIdx.x] = 0ull;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) counters[i] = 0ull;
 }
 
-// One persistent kernel per code path: blocks pop `chunk` tiles at a time
-// from the path's counter until the list is exhausted (every block leaves).
+__device__ inline int64_t uniform64(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// One persistent kernel per code path.  The path's tile list is split into
+// one contiguous range per XCD (hardware dispatches workgroup b to XCD
+// b % 8); a block pops `chunk` tiles at a time from its XCD's range, so
+// neighbouring tiles -- which read the same element matrices -- run on one
+// XCD and share its L2, as the single-mesh kernels' block order arranges;
+// when its range is exhausted it helps the other ranges, and leaves when
+// every range is.  The tile entry is wave-uniform, so the mesh's arguments
+// come through the scalar cache into scalar registers, as a kernel argument
+// would; the next tile's entry is loaded while the current one is assembled.
 template <int FMT, int PATH>
 __global__ void __launch_bounds__(64)
     k_batch(const MeshDesc* __restrict__ meshes, const double* const* __restrict__ ke,
             double* const* __restrict__ values, const BatchTile* __restrict__ tiles,
-            int64_t n_tiles, int64_t chunk, unsigned long long* counter) {
+            int64_t n_tiles, int64_t chunk, unsigned long long* counters) {
     extern __shared__ double lds[];
     __shared__ int64_t s_first;
-    for (;;) {
-        if (threadIdx.x == 0) s_first = (int64_t)atomicAdd(counter, (unsigned long long)chunk);
-        __syncthreads();
-        const int64_t first = s_first;
-        __syncthreads();
-        if (first >= n_tiles) break;
-        const int64_t last = first + chunk < n_tiles ? first + chunk : n_tiles;
-        for (int64_t t = first; t < last; ++t) {
-            const BatchTile T = tiles[t];
-            const MeshDesc* M = meshes + T.mesh;
-            if (PATH <= kRows2J2) {
-                OwnArgs A = M->own_args;
-                A.ke = ke[T.mesh];
-                A.values = values[T.mesh];
-                if (PATH == kOwnG4) owner_tiles<FMT, 4, 1, 8>(A, T.index, T.index + 1, lds);
-                if (PATH == kOwnG8) owner_tiles<FMT, 8, 1, 8>(A, T.index, T.index + 1, lds);
-                if (PATH == kOwnG16) owner_tiles<FMT, 16, 1, 8>(A, T.index, T.index + 1, lds);
-                if (PATH == kOwnG32) owner_tiles<FMT, 32, 1, 8>(A, T.index, T.index + 1, lds);
-                if (PATH == kOwnG64J1) owner_tiles<FMT, 64, 1, 8>(A, T.index, T.index + 1, lds);
-                if (PATH == kOwnG64J2) owner_tiles<FMT, 64, 2, 8>(A, T.index, T.index + 1, lds);
-                if (PATH == kOwnG64J4) owner_tiles<FMT, 64, 4, 4>(A, T.index, T.index + 1, lds);
-                if (PATH == kOwnG64J8) owner_tiles<FMT, 64, 8, 2>(A, T.index, T.index + 1, lds);
-                if (PATH == kOwnG64J16) owner_tiles<FMT, 64, 16, 1>(A, T.index, T.index + 1, lds);
-                if (PATH == kRows2J1) owner_rows_tile<FMT, 2, 1, 8>(A, T.index, lds);
-                if (PATH == kRows2J2) owner_rows_tile<FMT, 2, 2, 8>(A, T.index, lds);
-            } else {
-                AsmArgs A = M->asm_args;
-                A.ke = ke[T.mesh];
-                A.values = values[T.mesh];
-                if (T.colour >= 0) {
-                    const int64_t c0 = M->colour_ptr[T.colour], c1 = M->colour_ptr[T.colour + 1];
-                    A.elem_list = A.elem_list + c0;
-                    A.count = c1 - c0;
+    constexpr bool kOwn = PATH <= kPipe24;
+    const int home = (int)(blockIdx.x % kXcds);
+    for (int step = 0; step < kXcds; ++step) {
+        const int x = (home + step) % kXcds;
+        const int64_t lo = n_tiles * x / kXcds, hi = n_tiles * (x + 1) / kXcds;
+        for (;;) {
+            if (threadIdx.x == 0)
+                s_first = lo + (int64_t)atomicAdd(counters + x, (unsigned long long)chunk);
+            __syncthreads();
+            const int64_t first = uniform64(s_first);
+            __syncthreads();
+            if (first >= hi) break;
+            const int64_t last = first + chunk < hi ? first + chunk : hi;
+            BatchTile next = tiles[first];
+            for (int64_t t = first; t < last; ++t) {
+                // every lane read the same entry: tell the compiler, so that the
+                // mesh's arguments are scalar loads and stay in scalar registers
+                BatchTile T;
+                T.mesh = __builtin_amdgcn_readfirstlane(next.mesh);
+                T.colour = __builtin_amdgcn_readfirstlane(next.colour);
+                T.index = uniform64(next.index);
+                if (t + 1 < last) next = tiles[t + 1];
+                const int32_t cur = T.mesh;
+                if (kOwn) {
+                    OwnArgs O = meshes[cur].own_args;
+                    O.ke = ke[cur];
+                    O.values = values[cur];
+                    if (PATH == kOwnG4) owner_tiles<FMT, 4, 1, 8>(O, T.index, T.index + 1, lds);
+                    if (PATH == kOwnG8) owner_tiles<FMT, 8, 1, 8>(O, T.index, T.index + 1, lds);
+                    if (PATH == kOwnG16) owner_tiles<FMT, 16, 1, 8>(O, T.index, T.index + 1, lds);
+                    if (PATH == kOwnG32) owner_tiles<FMT, 32, 1, 8>(O, T.index, T.index + 1, lds);
+                    if (PATH == kOwnG64J1) owner_tiles<FMT, 64, 1, 8>(O, T.index, T.index + 1, lds);
+                    if (PATH == kOwnG64J2) owner_tiles<FMT, 64, 2, 8>(O, T.index, T.index + 1, lds);
+                    if (PATH == kOwnG64J4) owner_tiles<FMT, 64, 4, 4>(O, T.index, T.index + 1, lds);
+                    if (PATH == kOwnG64J8) owner_tiles<FMT, 64, 8, 2>(O, T.index, T.index + 1, lds);
+                    if (PATH == kOwnG64J16) owner_tiles<FMT, 64, 16, 1>(O, T.index, T.index + 1, lds);
+                    if (PATH == kRows2J1) owner_rows_tile<FMT, 2, 1, 8>(O, T.index, lds);
+                    if (PATH == kRows2J2) owner_rows_tile<FMT, 2, 2, 8>(O, T.index, lds);
+                    if (PATH == kPipe24) owner_pipe_row<FMT, 3, 24, 8, 0>(O, T.index, lds);
+                } else {
+                    AsmArgs A = meshes[cur].asm_args;
+                    A.ke = ke[cur];
+                    A.values = values[cur];
+                    if (T.colour >= 0) {
+                        const int64_t c0 = meshes[cur].colour_ptr[T.colour];
+                        const int64_t c1 = meshes[cur].colour_ptr[T.colour + 1];
+                        A.elem_list = A.elem_list + c0;
+                        A.count = c1 - c0;
+                    }
+                    int32_t* li = reinterpret_cast<int32_t*>(lds);
+                    if (PATH == kElemA16) elem_tile<FMT, true, 16, 1, 64>(A, T.index, li);
+                    if (PATH == kElemA32) elem_tile<FMT, true, 32, 2, 64>(A, T.index, li);
+                    if (PATH == kElemA64) elem_tile<FMT, true, 64, 16, 64>(A, T.index, li);
+                    if (PATH == kElemP16) elem_tile<FMT, false, 16, 1, 64>(A, T.index, li);
+                    if (PATH == kElemP32) elem_tile<FMT, false, 32, 2, 64>(A, T.index, li);
+                    if (PATH == kElemP64) elem_tile<FMT, false, 64, 16, 64>(A, T.index, li);
                 }
-                int32_t* li = reinterpret_cast<int32_t*>(lds);
-                if (PATH == kElemA16) elem_tile<FMT, true, 16, 1, 64>(A, T.index, li);
-                if (PATH == kElemA32) elem_tile<FMT, true, 32, 2, 64>(A, T.index, li);
-                if (PATH == kElemA64) elem_tile<FMT, true, 64, 16, 64>(A, T.index, li);
-                if (PATH == kElemP16) elem_tile<FMT, false, 16, 1, 64>(A, T.index, li);
-                if (PATH == kElemP32) elem_tile<FMT, false, 32, 2, 64>(A, T.index, li);
-                if (PATH == kElemP64) elem_tile<FMT, false, 64, 16, 64>(A, T.index, li);
+                __syncthreads();  // LDS is reused by the next tile
             }
-            __syncthreads();  // LDS is reused by the next tile
         }
     }
 }
@@ -220,6 +254,13 @@ int mesh_path(const feasm_pattern* p, int fmt, int strategy, MeshDesc& D, size_t
             A.idx_ints = (int32_t)idx;
             A.acc_doubles = p->d * p->d * p->max_deg;
             A.group_bytes = (int32_t)gb;
+            if (g == 64 && p->d == 3 && p->n == 24 && p->max_inc <= 8 && p->tune_owner_flat >= 0 &&
+                p->tune_owner_rows <= 1 && gb + 2 * 8 * p->k * 4 <= 64 * 1024) {
+                D.path = kPipe24;
+                lds = (size_t)gb + (size_t)2 * 8 * p->k * 4;
+                per = 1;  // one node row per tile
+                return FEASM_OK;
+            }
             const int rows = p->tune_owner_rows != 0 ? p->tune_owner_rows : (g == 64 && gb <= 3072 ? 2 : 1);
             if (g == 64 && rows == 2 && jj <= 2 && gb * 2 + 8 * p->k * 4 <= 64 * 1024) {
                 D.path = jj == 1 ? kRows2J1 : kRows2J2;
@@ -266,7 +307,7 @@ int build_graph(feasm_batch* b) {
     hipStream_t s0 = b->streams[0], s1 = b->streams[1], s2 = b->streams[2];
     FEASM_HIP(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
     const int32_t nl = (int32_t)b->launches.size();
-    k_batch_reset<<<1, 64, 0, s0>>>(b->d_counters, nl);
+    k_batch_reset<<<1, 256, 0, s0>>>(b->d_counters, nl * kXcds);
     if (b->n_zero > 0 && !b->accumulate)
         k_batch_zero<<<(unsigned)std::min<int64_t>(b->n_zero, 8192), 256, 0, s0>>>(b->d_zero, b->n_zero,
                                                                                   b->d_values);
@@ -285,7 +326,7 @@ int build_graph(feasm_batch* b) {
             }
             batch_kernel(b->fmt, L.path)<<<(unsigned)L.grid, 64, L.lds, s>>>(
                 b->d_meshes, b->d_ke, b->d_values, L.d_tiles, L.n_tiles, L.chunk,
-                b->d_counters + i);
+                b->d_counters + (int64_t)i * kXcds);
         }
         if (any && err == hipSuccess) {
             err = hipEventRecord(b->events[br], s);
@@ -523,7 +564,7 @@ int create(feasm_batch* b, const feasm_pattern* const* patterns, int64_t count, 
         b->launches.insert(b->launches.end(), here.begin(), here.end());
     }
     {
-        const int rc = dev_alloc_n(b->alloc, &b->d_counters, (int64_t)b->launches.size(), nullptr,
+        const int rc = dev_alloc_n(b->alloc, &b->d_counters, (int64_t)b->launches.size() * kXcds, nullptr,
                                    "batch_create");
         if (rc != FEASM_OK) return rc;
     }
