@@ -152,10 +152,13 @@ def main():
                     help="batch512: number of meshes (the mix is the first N of the 512)")
     ap.add_argument("--cpu-reps", type=int, default=3, help="0 skips the oracle baseline")
     ap.add_argument("--only", default="", help="comma-separated variants to time (default: all)")
-    ap.add_argument("--sections", default="reassembly,spmv",
+    ap.add_argument("--sections", default="reassembly,spmv,tet40,batch512,serve",
                     help="single-mesh workloads: the sections reported after the variants, "
-                         "comma-separated from reassembly, spmv (empty: none, e.g. for a "
-                         "profile of the assembly kernels alone)")
+                         "comma-separated from reassembly, spmv, and (hex64 only) tet40, "
+                         "batch512, serve (empty: none, e.g. for a profile of the assembly "
+                         "kernels alone)")
+    ap.add_argument("--section-serve-seconds", type=float, default=2.0,
+                    help="length of each serving scenario in the serve section")
     ap.add_argument("--hex8-pipe", type=int, default=0,
                     help="hex8 workload: fused-kernel setting (0 auto, n blocks per CU, -1 off)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -208,6 +211,10 @@ def main():
         pb_ms.append((time.perf_counter() - t0) * 1e3)
         if _ < 2:
             p.free()
+    # the same pattern with element tiles: the atomic scatter with per-tile
+    # LDS sums (one write per distinct entry of a tile)
+    p_t = feasm.pattern_build(conn_d, w.dofs_per_node, w.n_nodes,
+                              feasm.BUILD_CSR | feasm.BUILD_CRAC | feasm.BUILD_TILES)
     values = torch.zeros(p.nnz, dtype=torch.float64, device=dev)
 
     A, C, O, S, ACC = (feasm.SCATTER_ATOMIC, feasm.SCATTER_COLOURED, feasm.SCATTER_OWNER,
@@ -217,6 +224,8 @@ def main():
         "crac_owner": lambda: feasm.assemble_crac(p, ke_d, values, O),
         "csr_atomic": lambda: feasm.assemble_csr(p, ke_d, values, A),
         "crac_atomic": lambda: feasm.assemble_crac(p, ke_d, values, A),
+        "csr_atomic_tiled": lambda: feasm.assemble_csr(p_t, ke_d, values, A),
+        "crac_atomic_tiled": lambda: feasm.assemble_crac(p_t, ke_d, values, A),
         "csr_coloured": lambda: feasm.assemble_csr(p, ke_d, values, C),
         "crac_coloured": lambda: feasm.assemble_crac(p, ke_d, values, C),
         "csr_spin": lambda: feasm.assemble_csr(p, ke_d, values, S),
@@ -227,6 +236,8 @@ def main():
         "crac_owner": lambda: feasm.assemble_crac(p, ke_d, values, O),
         "csr_atomic": lambda: feasm.assemble_csr(p, ke_d, values, A | ACC),
         "crac_atomic": lambda: feasm.assemble_crac(p, ke_d, values, A | ACC),
+        "csr_atomic_tiled": lambda: feasm.assemble_csr(p_t, ke_d, values, A | ACC),
+        "crac_atomic_tiled": lambda: feasm.assemble_crac(p_t, ke_d, values, A | ACC),
         "csr_coloured": lambda: feasm.assemble_csr(p, ke_d, values, C | ACC),
         "crac_coloured": lambda: feasm.assemble_crac(p, ke_d, values, C | ACC),
         "csr_spin": lambda: feasm.assemble_csr(p, ke_d, values, S | ACC),
@@ -241,7 +252,7 @@ def main():
         log(f"[bench] variant {name}")
         t_full = stats(time_calls(fn, reps, args.warmup))
         t_sc = stats(time_calls(scatter_only[name], reps, args.warmup))
-        fmt, strategy = name.split("_")
+        fmt, strategy = name.split("_", 1)
         nbytes = algorithmic_bytes(w, p, fmt, strategy)
         variants[name] = {
             "assemble_ms": t_full,
@@ -253,13 +264,13 @@ def main():
             # the element matrices alone: the stream every strategy must read
             "Ke_only_GBps": w.n_elem * w.n * w.n * 8 / (t_sc["mean"] * 1e-3) / 1e9,
         }
-        if strategy == "atomic":
+        if strategy.startswith("atomic"):
             # one FP64 atomic add per element-matrix entry (the second ceiling
             # of this method besides HBM bandwidth)
             variants[name]["atomic_adds_per_launch"] = w.n_elem * w.n * w.n
             variants[name]["atomic_adds_per_s"] = w.n_elem * w.n * w.n / (t_sc["mean"] * 1e-3)
     sections = set(filter(None, args.sections.split(",")))
-    unknown = sections - {"reassembly", "spmv"}
+    unknown = sections - {"reassembly", "spmv", "tet40", "batch512", "serve"}
     if unknown:
         raise SystemExit(f"--sections: unknown {sorted(unknown)}")
     reasm = {}
@@ -304,7 +315,7 @@ def main():
     ms_per_step = t0.elapsed_time(t1) / args.steps
 
     v = variants[best]
-    fmt, strategy = best.split("_")
+    fmt, strategy = best.split("_", 1)
     kernel_ms = v["scatter_only_ms"]["mean"]
     spec_bytes = algorithmic_bytes(w, p, fmt, "atomic")
     achieved = v["algorithmic_bytes"] / (kernel_ms * 1e-3) / 1e9
@@ -358,7 +369,69 @@ def main():
         log("[bench] CPU baseline (serial oracle)")
         line["cpu_baseline"] = cpu_baseline(w, ke, args.cpu_reps)
     p.free()
+    p_t.free()
+    del ke_d, values, ke
+    if args.workload == "hex64":
+        # the other workloads, compact, in the same line
+        if "tet40" in sections:
+            line["tet40"] = tet40_section(args)
+        if "batch512" in sections:
+            out, (pats, _k, _v, b, _s) = batch_section(args, colour=False)
+            b.free()
+            for q in pats:
+                q.free()
+            del _k, _v
+            line["batch512"] = out
+        if "serve" in sections:
+            line["serve"] = serve_section(args, args.serve_rate, args.section_serve_seconds)
     print(json.dumps(line), flush=True)
+
+
+def tet40_section(args):
+    """The permuted tet10 mesh (40^3 cubes x 6, 3 DOFs per node), element
+    matrices from the device generator (30 x 30 SPD, key 0): step time and
+    HBM roofline fraction of the row-owned assembly, and the atomic
+    strategy beside it."""
+    import torch
+
+    import paper_2012_00585_amd as feasm
+
+    w, wdesc = workload("tet40")
+    dev = torch.device("cuda:0")
+    log("[bench] tet40 section: pattern build")
+    conn_d = torch.from_numpy(w.conn).to(dev)
+    t0 = time.perf_counter()
+    p = feasm.pattern_build(conn_d, w.dofs_per_node, w.n_nodes, feasm.BUILD_CSR | feasm.BUILD_CRAC)
+    build_ms = (time.perf_counter() - t0) * 1e3
+    ke_d = feasm.generate_ke(feasm.RECIPE_SPD, w.n_elem, w.n, 0)
+    values = torch.zeros(p.nnz, dtype=torch.float64, device=dev)
+    O, A, ACC = feasm.SCATTER_OWNER, feasm.SCATTER_ATOMIC, feasm.ACCUMULATE
+    reps = max(args.steps, 5)
+    out = {"workload": wdesc.replace("30x30 SPD FP64 Ke, seed 0",
+                                     "30x30 SPD FP64 Ke from the device generator, key 0"),
+           "n_elem": w.n_elem, "nnz": p.nnz, "n_ca": p.n_ca, "pattern_build_ms": build_ms}
+    for name, fn, sc in (("crac_owner", feasm.assemble_crac, O), ("csr_owner", feasm.assemble_csr, O),
+                         ("crac_atomic", feasm.assemble_crac, A),
+                         ("csr_atomic", feasm.assemble_csr, A)):
+        full = stats(time_calls(lambda f=fn, c=sc: f(p, ke_d, values, c), reps, args.warmup))
+        # the row-owned strategy writes every value once and has no reset
+        # pass: its full assembly is its scatter
+        sco = full if sc == O else stats(time_calls(lambda f=fn, c=sc: f(p, ke_d, values, c | ACC),
+                                                    reps, args.warmup))
+        fmt, strategy = name.split("_")
+        nb = algorithmic_bytes(w, p, fmt, strategy)
+        out[name] = {"assemble_ms": full["mean"], "scatter_only_ms": sco["mean"],
+                     "algorithmic_bytes": nb,
+                     "GBps": nb / (sco["mean"] * 1e-3) / 1e9,
+                     "roofline_frac": nb / (sco["mean"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        log(f"[bench]   tet40 {name}: {full['mean']:.3f} ms (scatter only {sco['mean']:.3f} ms, "
+            f"{out[name]['roofline_frac']:.2f} of HBM peak)")
+    best = min(("crac_owner", "csr_owner"), key=lambda k: out[k]["assemble_ms"])
+    out["step_variant"] = best
+    out["step_ms"] = out[best]["assemble_ms"]
+    out["elements_per_s"] = w.n_elem / (out["step_ms"] * 1e-3)
+    p.free()
+    return out
 
 
 def _oracle_mesh(spec):
@@ -401,8 +474,10 @@ def batch_cpu_baseline(specs, count):
                        f"phase; wall {wall:.1f} s, {busy:.1f} s of oracle work")}
 
 
-def bench_batch(args):
-    """Many meshes in one persistent, graph-captured launch vs one launch per mesh."""
+def batch_section(args, colour=True, log_prefix="[bench]"):
+    """Many meshes in one persistent, graph-captured launch vs one launch per
+    mesh, on the 512-mesh mix (quads n in [16,512], d=1; hexes m in [8,48],
+    d=3; device-generated element matrices), CRAC, autotuned inside the batch."""
     import torch
 
     import paper_2012_00585_amd as feasm
@@ -412,8 +487,8 @@ def bench_batch(args):
 
     dev = torch.device("cuda:0")
     specs = configs.batch_mix()[: args.batch_count]
-    log(f"[bench] batch of {len(specs)} meshes: building patterns")
-    flags = feasm.BUILD_CSR | feasm.BUILD_CRAC | feasm.BUILD_COLOUR
+    log(f"{log_prefix} batch of {len(specs)} meshes: building patterns")
+    flags = feasm.BUILD_CSR | feasm.BUILD_CRAC | (feasm.BUILD_COLOUR if colour else 0)
     pats, kes, vals = [], [], []
     t0 = time.perf_counter()
     for i, sp in enumerate(specs):
@@ -423,38 +498,60 @@ def bench_batch(args):
         kes.append(feasm.generate_ke(recipe, p.n_elem, p.n, sp.seed))
         vals.append(torch.empty(p.nnz, dtype=torch.float64, device=dev))
         pats.append(p)
-        if (i + 1) % 64 == 0:
-            log(f"[bench]   {i + 1} meshes")
+        if (i + 1) % 128 == 0:
+            log(f"{log_prefix}   {i + 1} meshes")
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     E = sum(p.n_elem for p in pats)
     nnz = sum(p.nnz for p in pats)
     ke_bytes = sum(p.n_elem * p.n * p.n * 8 for p in pats)
-    log(f"[bench] {E} elements, nnz {nnz}, Ke {ke_bytes / 1e9:.1f} GB; autotuning")
+    log(f"{log_prefix} {E} elements, nnz {nnz}, Ke {ke_bytes / 1e9:.1f} GB; autotuning in the batch")
     fmt = feasm.FMT_CRAC
-    choices = autotune.autotune(pats, kes, vals, fmt, reps=3, warmup=1, log=log)
+    # the tuner times its candidates inside the persistent batch itself
+    choices, _ = autotune.autotune_batch(pats, kes, vals, fmt, lambda ps: Batch(ps, fmt=fmt),
+                                         reps=3, warmup=1, log=log)
     b = Batch(pats, fmt=fmt)
     info = b.info()
-    log(f"[bench] batch: {info['phases']} phase(s), {info['tiles']} tiles, grid {info['grid']}")
-    persistent = stats(time_calls(lambda: b.assemble(kes, vals), max(args.steps, 5), args.warmup))
+    log(f"{log_prefix} batch: {info['phases']} phase(s), {info['tiles']} tiles, grid {info['grid']}")
+    reps = max(args.steps, 5)
+    persistent = stats(time_calls(lambda: b.assemble(kes, vals), reps, args.warmup))
     g = Batch(pats, fmt=fmt, per_mesh_graph=True)
-    graph = stats(time_calls(lambda: g.assemble(kes, vals), max(args.steps, 5), args.warmup))
-    log(f"[bench] persistent per-path launches {persistent['mean']:.3f} ms, "
-        f"per-mesh graph {graph['mean']:.3f} ms")
-    # the batch mode is a launch-shape choice: keep the faster
-    if graph["mean"] < persistent["mean"]:
-        b.free()
-        b, mode, batched = g, "per_mesh_graph", graph
-    else:
-        g.free()
-        mode, batched = "persistent", persistent
+    graph = stats(time_calls(lambda: g.assemble(kes, vals), reps, args.warmup))
+    g.free()
 
     def one_per_launch():
         for p, k, v in zip(pats, kes, vals):
             feasm.assemble_crac(p, k, v)
 
-    single = stats(time_calls(one_per_launch, max(args.steps // 4, 3), 1))
-    # timed steps: the batched replay
+    single = stats(time_calls(one_per_launch, max(reps // 4, 3), 1))
+    log(f"{log_prefix} persistent {persistent['mean']:.3f} ms, per-mesh graph {graph['mean']:.3f} "
+        f"ms, one launch per mesh {single['mean']:.3f} ms")
+    nbytes = sum(p.n_elem * p.n * p.n * 8 + p.nnz * 8 for p in pats)
+    out = {
+        "workload": f"batch mix: {len(specs)} meshes (quads n in [16,512], d=1, 4x4; hexes m in "
+                    f"[8,48], d=3, 24x24), CRAC, device-generated Ke",
+        "n_elem": E, "nnz": nnz, "ke_GB": ke_bytes / 1e9,
+        "phases": info["phases"], "tiles": info["tiles"], "grid": info["grid"],
+        "paths": {k: info["paths"].count(k) for k in sorted(set(info["paths"]))},
+        "persistent_ms": persistent,
+        "per_mesh_graph_ms": graph,
+        "one_mesh_per_launch_ms": single,
+        "persistent_speedup_vs_one_per_launch": single["mean"] / persistent["mean"],
+        "persistent_Ke_plus_values_GBps": nbytes / (persistent["mean"] * 1e-3) / 1e9,
+        "autotune_in_batch": {f"k{c[0]}_d{c[1]}_b{c[2]}": [x.label() + f" {x.ms:.3f}ms"
+                                                           for x in v[:3]]
+                              for c, v in choices.items()},
+        "build_s": build_s,
+    }
+    return out, (pats, kes, vals, b, specs)
+
+
+def bench_batch(args):
+    """Many meshes in one persistent, graph-captured launch vs one launch per mesh."""
+    import torch
+
+    out, (pats, kes, vals, b, specs) = batch_section(args)
+    # timed steps: the persistent batched replay
     for _ in range(args.warmup):
         b.assemble(kes, vals)
     torch.cuda.synchronize()
@@ -466,27 +563,16 @@ def bench_batch(args):
     a1.record()
     torch.cuda.synchronize()
     ms = a0.elapsed_time(a1) / args.steps
-    nbytes = sum(p.n_elem * p.n * p.n * 8 + p.nnz * 8 for p in pats)
     line = {
         "metric": "element matrices assembled/s (batched, 512 meshes)",
-        "value": E / (ms * 1e-3), "unit": "element matrices/s", "n_gpus": 1,
+        "value": out["n_elem"] / (ms * 1e-3), "unit": "element matrices/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"batch mix: {len(specs)} meshes (quads n in [16,512], d=1, 4x4; "
-                               f"hexes m in [8,48], d=3, 24x24), CRAC, device-generated Ke",
-                   "n_elem": E, "nnz": nnz, "ke_GB": ke_bytes / 1e9,
-                   "phases": info["phases"], "tiles": info["tiles"], "grid": info["grid"]},
-        "batch_mode": mode,
-        "batched_ms": batched,
-        "persistent_ms": persistent,
-        "per_mesh_graph_ms": graph,
-        "one_mesh_per_launch_ms": single,
-        "speedup_vs_one_per_launch": single["mean"] / batched["mean"],
-        "Ke_plus_values_GBps": nbytes / (ms * 1e-3) / 1e9,
-        "autotune": {f"k{c[0]}_d{c[1]}_b{c[2]}": [x.label() + f" {x.ms:.3f}ms" for x in v[:3]]
-                     for c, v in choices.items()},
-        "build_s": build_s,
+        "config": {"workload": out["workload"], "n_elem": out["n_elem"], "nnz": out["nnz"],
+                   "ke_GB": out["ke_GB"], "phases": out["phases"], "tiles": out["tiles"],
+                   "grid": out["grid"]},
+        "batch": out,
     }
     b.free()
     for p in pats:
@@ -644,8 +730,15 @@ def bench_hex8(args):
     print(json.dumps(line), flush=True)
 
 
-def bench_serve(args):
-    """Poisson request stream over the batch mix: assembly + 10 re-assemblies each."""
+def serve_section(args, rate, seconds, log_prefix="[bench]"):
+    """Serving on the 512-mesh batch mix: Poisson arrivals, assembly + 10
+    re-assemblies per request.  Scenarios: continuous batching with fresh
+    element matrices generated on the device per iteration (generator time
+    reported apart), the same at 500 req/s (unsaturated), continuous batching
+    on pre-generated per-mesh element-matrix pools (assembly-side capacity,
+    no generator in the loop), patterns built on demand in a byte-bounded
+    cache, and one request at a time on one stream (FIFO, the
+    one-mesh-per-launch baseline)."""
     import torch
 
     import paper_2012_00585_amd as feasm
@@ -655,11 +748,13 @@ def bench_serve(args):
 
     dev = torch.device("cuda:0")
     specs = configs.batch_mix()[: args.batch_count]
-    log(f"[bench] serve: building {len(specs)} resident patterns")
-    pats, recipes = [], []
+    log(f"{log_prefix} serve: building {len(specs)} resident patterns")
+    pats, recipes, conns = [], [], []
     for sp in specs:
         conn, nn = meshes.quad_mesh(sp.size) if sp.kind == "quad" else meshes.hex_mesh(sp.size)
-        pats.append(feasm.pattern_build(torch.from_numpy(conn).to(dev), sp.dofs_per_node, nn,
+        conn_d = torch.from_numpy(conn).to(dev)
+        conns.append((conn_d, sp.dofs_per_node, nn))
+        pats.append(feasm.pattern_build(conn_d, sp.dofs_per_node, nn,
                                         feasm.BUILD_CSR | feasm.BUILD_CRAC))
         recipes.append(feasm.RECIPE_LAPLACIAN if sp.kind == "quad" else feasm.RECIPE_SPD)
     # one tuning pass per size class on generated matrices
@@ -674,31 +769,57 @@ def bench_serve(args):
         for i in members:
             autotune.apply(pats[i], ranked[0])
         del ke, vals
+    # per-mesh pools of two pre-generated blocks (about 85 GB for the mix)
+    pools = [torch.stack([feasm.generate_ke(recipes[i], p.n_elem, p.n, 7000 + 2 * i + b)
+                          for b in range(2)]) for i, p in enumerate(pats)]
+    torch.cuda.synchronize()
 
-    def stream(rate, seconds, seed):
-        n = int(rate * seconds)
-        t = configs.arrival_times(n, 1.0 / rate, seed=seed)
+    def stream(rate_, seconds_, seed):
+        n = int(rate_ * seconds_)
+        t = configs.arrival_times(n, 1.0 / rate_, seed=seed)
         rng = np.random.default_rng(seed + 1)
         mesh = rng.integers(len(specs), size=n)
         rs = rng.integers(1 << 40, size=n)
         return [Request(i, float(t[i]), int(mesh[i]), int(rs[i]), 10) for i in range(n)]
 
-    def server(slots):
-        srv = Server(fmt=feasm.FMT_CRAC, slots=slots, hbm_budget=96 << 30)
+    def server(slots, pool=False, cache=None):
+        srv = Server(fmt=feasm.FMT_CRAC, slots=slots, hbm_budget=96 << 30,
+                     pattern_cache_bytes=cache)
         for i, p in enumerate(pats):
-            srv.register(i, p, recipes[i])
+            if cache is not None:
+                srv.register_mesh(i, conns[i][0], conns[i][1], conns[i][2], recipes[i])
+            else:
+                srv.register(i, p, recipes[i], ke_pool=pools[i] if pool else None)
         return srv
 
     out = {}
-    for name, rate, seconds, slots in (
-            ("continuous", args.serve_rate, args.serve_seconds, args.serve_slots),
-            ("continuous_500", 500.0, args.serve_seconds / 2, args.serve_slots),
-            ("fifo_one_per_launch", args.serve_rate, args.serve_seconds / 5, 1)):
-        log(f"[bench] serve {name}: {rate:.0f} req/s for {seconds:.1f} s, {slots} slot(s); warm-up")
-        server(slots).run(stream(rate, 1.0, seed=99))
-        res = server(slots).run(stream(rate, seconds, seed=0))
-        log(f"[bench]   {res}")
+    for name, rate_, secs, slots, pool, cache in (
+            ("continuous", rate, seconds, args.serve_slots, False, None),
+            ("continuous_500", 500.0, seconds / 2, args.serve_slots, False, None),
+            ("continuous_pooled_K", rate, seconds, args.serve_slots, True, None),
+            ("continuous_pattern_cache_16GB", rate, seconds / 2, args.serve_slots, False, 16 << 30),
+            ("fifo_one_per_launch", rate, seconds / 5, 1, False, None)):
+        log(f"{log_prefix} serve {name}: {rate_:.0f} req/s for {secs:.1f} s, {slots} slot(s); "
+            "warm-up")
+        server(slots, pool, cache).run(stream(rate_, min(1.0, secs), seed=99))
+        res = server(slots, pool, cache).run(stream(rate_, secs, seed=0))
+        eng = res["engine"]
+        if eng["assemble_ms"] > 0:
+            res["generator_share_of_device_time"] = eng["generate_ms"] / (eng["generate_ms"] +
+                                                                          eng["assemble_ms"])
+        log(f"{log_prefix}   {name}: {res['achieved_req_per_s']:.0f} req/s, re-assembly p50 "
+            f"{res['reassembly_ms']['p50']:.3f} p99 {res['reassembly_ms']['p99']:.3f} ms, "
+            f"generator {eng['generate_ms']:.0f} ms vs assembly {eng['assemble_ms']:.0f} ms")
         out[name] = res
+    for p in pats:
+        p.free()
+    del pools
+    return out
+
+
+def bench_serve(args):
+    """Poisson request stream over the batch mix: assembly + 10 re-assemblies each."""
+    out = serve_section(args, args.serve_rate, args.serve_seconds)
     c = out["continuous"]
     line = {
         "metric": "served element matrices/s; p50/p99 re-assembly latency",
@@ -707,13 +828,11 @@ def bench_serve(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"serving: Poisson arrivals at {args.serve_rate:.0f} req/s over "
-                               f"the {len(specs)}-mesh batch mix, assembly + 10 re-assemblies "
-                               f"with device-generated Ke, resident CRAC patterns",
+                               f"the {args.batch_count}-mesh batch mix, assembly + 10 "
+                               f"re-assemblies with device-generated Ke, resident CRAC patterns",
                    "slots": args.serve_slots, "seconds": args.serve_seconds},
         "scenarios": out,
     }
-    for p in pats:
-        p.free()
     print(json.dumps(line), flush=True)
 
 
