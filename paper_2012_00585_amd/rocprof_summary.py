@@ -221,7 +221,7 @@ def shares(trace, window_s, command, workload, title=None):
     where = (f"the {window_s:g} s window with the most dispatches" if window_s
              else "the whole trace")
     lines.append(f"Over {where}: {len(sel)} dispatches, device busy (union of kernel "
-                 f"intervals) {busy / span:.3f} of {span / 1e6:.1f} ms; kernels of "
+                 f"intervals) for {100 * busy / span:.1f}% of its {span / 1e6:.1f} ms; kernels of "
                  f"concurrent streams overlap, so the summed time ({summed:.1f} ms) exceeds it.")
     lines.append("")
     lines.append("| kernel | summed ms | share | dispatches | mean us |")
