@@ -475,8 +475,9 @@ def batch_cpu_baseline(specs, count):
 
 
 def batch_section(args, colour=True, log_prefix="[bench]"):
-    """Many meshes in one persistent, graph-captured launch vs one launch per
-    mesh, on the 512-mesh mix (quads n in [16,512], d=1; hexes m in [8,48],
+    """Many meshes in one graph-captured launch (a workgroup per tile; also
+    persistent, and every mesh's own kernels) vs one launch per mesh, on the
+    512-mesh mix (quads n in [16,512], d=1; hexes m in [8,48],
     d=3; device-generated element matrices), CRAC, autotuned inside the batch."""
     import torch
 
@@ -507,14 +508,19 @@ def batch_section(args, colour=True, log_prefix="[bench]"):
     ke_bytes = sum(p.n_elem * p.n * p.n * 8 for p in pats)
     log(f"{log_prefix} {E} elements, nnz {nnz}, Ke {ke_bytes / 1e9:.1f} GB; autotuning in the batch")
     fmt = feasm.FMT_CRAC
-    # the tuner times its candidates inside the persistent batch itself
+    # the tuner times its candidates inside the batch itself
     choices, _ = autotune.autotune_batch(pats, kes, vals, fmt, lambda ps: Batch(ps, fmt=fmt),
                                          reps=3, warmup=1, log=log)
     b = Batch(pats, fmt=fmt)
     info = b.info()
-    log(f"{log_prefix} batch: {info['phases']} phase(s), {info['tiles']} tiles, grid {info['grid']}")
+    log(f"{log_prefix} batch: {info['phases']} phase(s), {info['tiles']} tiles, largest launch "
+        f"{info['grid']} workgroups")
     reps = max(args.steps, 5)
-    persistent = stats(time_calls(lambda: b.assemble(kes, vals), reps, args.warmup))
+    tiles = stats(time_calls(lambda: b.assemble(kes, vals), reps, args.warmup))
+    q = Batch(pats, fmt=fmt, persistent=True)
+    pinfo = q.info()
+    persistent = stats(time_calls(lambda: q.assemble(kes, vals), reps, args.warmup))
+    q.free()
     g = Batch(pats, fmt=fmt, per_mesh_graph=True)
     graph = stats(time_calls(lambda: g.assemble(kes, vals), reps, args.warmup))
     g.free()
@@ -524,20 +530,22 @@ def batch_section(args, colour=True, log_prefix="[bench]"):
             feasm.assemble_crac(p, k, v)
 
     single = stats(time_calls(one_per_launch, max(reps // 4, 3), 1))
-    log(f"{log_prefix} persistent {persistent['mean']:.3f} ms, per-mesh graph {graph['mean']:.3f} "
-        f"ms, one launch per mesh {single['mean']:.3f} ms")
+    log(f"{log_prefix} tile grid {tiles['mean']:.3f} ms, persistent {persistent['mean']:.3f} ms, "
+        f"per-mesh graph {graph['mean']:.3f} ms, one launch per mesh {single['mean']:.3f} ms")
     nbytes = sum(p.n_elem * p.n * p.n * 8 + p.nnz * 8 for p in pats)
     out = {
         "workload": f"batch mix: {len(specs)} meshes (quads n in [16,512], d=1, 4x4; hexes m in "
                     f"[8,48], d=3, 24x24), CRAC, device-generated Ke",
         "n_elem": E, "nnz": nnz, "ke_GB": ke_bytes / 1e9,
         "phases": info["phases"], "tiles": info["tiles"], "grid": info["grid"],
+        "persistent_grid": pinfo["grid"],
         "paths": {k: info["paths"].count(k) for k in sorted(set(info["paths"]))},
+        "tile_grid_ms": tiles,
         "persistent_ms": persistent,
         "per_mesh_graph_ms": graph,
         "one_mesh_per_launch_ms": single,
-        "persistent_speedup_vs_one_per_launch": single["mean"] / persistent["mean"],
-        "persistent_Ke_plus_values_GBps": nbytes / (persistent["mean"] * 1e-3) / 1e9,
+        "tile_grid_speedup_vs_one_per_launch": single["mean"] / tiles["mean"],
+        "tile_grid_Ke_plus_values_GBps": nbytes / (tiles["mean"] * 1e-3) / 1e9,
         "autotune_in_batch": {f"k{c[0]}_d{c[1]}_b{c[2]}": [x.label() + f" {x.ms:.3f}ms"
                                                            for x in v[:3]]
                               for c, v in choices.items()},
@@ -547,11 +555,11 @@ def batch_section(args, colour=True, log_prefix="[bench]"):
 
 
 def bench_batch(args):
-    """Many meshes in one persistent, graph-captured launch vs one launch per mesh."""
+    """Many meshes in one graph-captured launch vs one launch per mesh."""
     import torch
 
     out, (pats, kes, vals, b, specs) = batch_section(args)
-    # timed steps: the persistent batched replay
+    # timed steps: the batched replay (a workgroup per tile)
     for _ in range(args.warmup):
         b.assemble(kes, vals)
     torch.cuda.synchronize()

@@ -392,19 +392,31 @@ int assemble_spin_noalloc(const feasm_pattern* p, int fmt, const double* ke, dou
 void pattern_free(feasm_pattern* p);
 
 /*
- * Batched assembly: many independent meshes in one persistent launch.
+ * Batched assembly: many independent meshes in one graph launch.
  *
  * batch_create prepares the batch for `count` handles (host array; the
  * handles must outlive the batch and all share `fmt`, FEASM_FMT_CSR or
  * FEASM_FMT_CRAC).  Each mesh runs the strategy its handle's
  * FEASM_TUNE_STRATEGY selects (AUTO = row-owned; row-owned meshes whose rows
  * do not fit the LDS accumulator fall back to atomics) with its launch-shape
- * knobs, except that element lanes are capped at 64.  `flags` may hold
- * FEASM_ACCUMULATE (no reset).  The work of the whole batch -- counter reset,
- * zero fill of the atomic and coloured meshes, one persistent launch per
- * kernel path (and per colour for coloured meshes, chained) pulling work
- * tiles from device counters -- is captured into one hipGraph.
- * Synchronises the device.
+ * knobs, except that element lanes are capped at 64.  The meshes' work is
+ * cut into tiles (node rows of row-owned meshes, element blocks otherwise)
+ * grouped by kernel path.  The whole sequence -- zero fill of the atomic and
+ * coloured meshes, then for each path of the row-owned and atomic meshes
+ * one launch over all of its tiles, and beside them, on a second graph
+ * branch, one launch per colour for coloured meshes in colour order -- is
+ * captured into one hipGraph.  `flags` may hold
+ * FEASM_ACCUMULATE (no reset) and one mode:
+ *   (none)                      a workgroup per tile, scheduled by the
+ *                               hardware dispatcher (fastest measured);
+ *   FEASM_BATCH_PERSISTENT      persistent launches: as many workgroups as
+ *                               are resident, popping tiles from device
+ *                               counters (one per XCD and path);
+ *   FEASM_BATCH_PER_MESH_GRAPH  every mesh's own single-mesh kernels
+ *                               (largest first, on 4 parallel branches); the
+ *                               graph is recaptured whenever the pointer
+ *                               tables change.
+ * Synchronises the device.  EINVAL for an unknown flag or both modes.
  *
  * assemble_batch replays it on `stream`: ke[i] (dev double [n_elem_i][n][n])
  * and values[i] (dev double [nnz_i]) are host arrays of device pointers; the
@@ -413,15 +425,11 @@ void pattern_free(feasm_pattern* p);
  * call they are uploaded first (and the host waits for that upload).  Calls
  * on one batch must not overlap.
  *
- * With flags | FEASM_BATCH_PER_MESH_GRAPH the graph instead holds every
- * mesh's own single-mesh kernels (largest first, on 4 parallel branches);
- * it is recaptured whenever the pointer tables change.
- *
- * batch_info reports the number of phases, work tiles, persistent grid
- * size and each mesh's kernel path (host array of `count` ints, may be NULL;
+ * batch_info reports the number of phases, work tiles, the largest launch's
+ * grid and each mesh's kernel path (host array of `count` ints, may be NULL;
  * zeros in per-mesh-graph mode).
  */
-enum { FEASM_BATCH_PER_MESH_GRAPH = 0x200 };
+enum { FEASM_BATCH_PER_MESH_GRAPH = 0x200, FEASM_BATCH_PERSISTENT = 0x400 };
 /*
  * Workload generator (benchmarks and serving; not part of the assembly
  * method): fills ke (dev double [n_elem][n][n]) with reproducible element

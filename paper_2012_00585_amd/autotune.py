@@ -124,40 +124,44 @@ def autotune(patterns, kes, values, fmt, reps=5, warmup=2, max_tpe=64, log=None)
     return out
 
 
-def autotune_batch(patterns, kes, values, fmt, make_batch, reps=3, warmup=1, top=3, log=None):
+def autotune_batch(patterns, kes, values, fmt, make_batch, reps=3, warmup=1, top=3, rounds=3,
+                   log=None):
     """Tune for the batched launch: single-mesh ranking per class first, then,
     class by class (largest work first), each of the class's ``top`` leading
     candidates (and the row-owned one with one row per wavefront) applied to
-    the whole class and timed as a replay of ``make_batch(patterns)``; the
-    fastest replay's candidate stays.  Returns ({class: [Choice ranked by
-    batch time]}, batch time in ms of the final choice)."""
+    the whole class, one ``make_batch(patterns)`` each; the batches are
+    replayed in turn for ``rounds`` rounds (so that clock drift hits every
+    candidate alike) and each keeps its fastest round; the fastest candidate
+    stays.  Returns ({class: [Choice ranked by batch time]}, batch time in ms
+    of the final choice)."""
     single = autotune(patterns, kes, values, fmt, reps=reps, warmup=warmup, max_tpe=64, log=log)
     classes = {}
     for i, p in enumerate(patterns):
         classes.setdefault(size_class(p), []).append(i)
     work = {c: sum(patterns[i].n_elem * patterns[i].n ** 2 for i in m) for c, m in classes.items()}
 
-    def batch_ms():
-        b = make_batch(patterns)
-        try:
-            return _time(lambda: b.assemble(kes, values), reps, warmup)
-        finally:
-            b.free()
-
     out = {}
-    current = batch_ms()
+    current = None
     for cls in sorted(classes, key=lambda c: -work[c]):
         members = classes[cls]
         tried = list(single[cls][:top])
         if not any(c.strategy == SCATTER_OWNER and c.rows in (0, 1) for c in tried):
             tried += [c for c in single[cls] if c.strategy == SCATTER_OWNER and c.rows in (0, 1)][:1]
-        timed = []
-        for c in tried:
-            for i in members:
-                apply(patterns[i], c)
-            t = batch_ms()
-            timed.append(Choice(c.strategy, c.tpe, c.rows, c.batch, t))
-        timed.sort(key=lambda c: c.ms)
+        batches = []
+        try:
+            for c in tried:
+                for i in members:
+                    apply(patterns[i], c)
+                batches.append(make_batch(patterns))  # the batch keeps the tuning it was built with
+            best = [float("inf")] * len(tried)
+            for _ in range(rounds):
+                for j, b in enumerate(batches):
+                    best[j] = min(best[j], _time(lambda: b.assemble(kes, values), reps, warmup))
+        finally:
+            for b in batches:
+                b.free()
+        timed = sorted((Choice(c.strategy, c.tpe, c.rows, c.batch, t) for c, t in zip(tried, best)),
+                       key=lambda c: c.ms)
         for i in members:
             apply(patterns[i], timed[0])
         current = timed[0].ms

@@ -1,12 +1,14 @@
-"""Batched assembly of many meshes in one persistent, graph-captured launch.
+"""Batched assembly of many meshes in one graph-captured launch.
 
     b = Batch(patterns, fmt=FMT_CRAC)        # patterns: list of Pattern
     b.assemble(kes, values)                  # lists of device tensors, one per mesh
     b.free()
 
 Each mesh runs the strategy and launch shape its handle was tuned to (see
-``autotune``).  Argument marshalling only; the work runs in libfeasm's
-batch kernel.
+``autotune``).  Modes: one launch per kernel path with a workgroup per work
+tile (default), persistent launches pulling tiles from device counters
+(``persistent=True``), or every mesh's own kernels (``per_mesh_graph=True``).
+Argument marshalling only; the work runs in libfeasm's batch kernels.
 """
 from __future__ import annotations
 
@@ -24,13 +26,15 @@ PATH_NAMES = ["own_g4", "own_g8", "own_g16", "own_g32", "own_g64_j1", "own_g64_j
 
 class Batch:
     def __init__(self, patterns: list[Pattern], fmt: int = FMT_CRAC, accumulate: bool = False,
-                 per_mesh_graph: bool = False):
+                 per_mesh_graph: bool = False, persistent: bool = False):
         self.patterns = list(patterns)
         n = len(self.patterns)
         arr = (ctypes.c_void_p * n)(*[p.handle.value for p in self.patterns])
         h = ctypes.c_void_p()
-        flags = (0x100 if accumulate else 0) | (0x200 if per_mesh_graph else 0)
+        flags = ((0x100 if accumulate else 0) | (0x200 if per_mesh_graph else 0)
+                 | (0x400 if persistent else 0))
         self.per_mesh_graph = per_mesh_graph
+        self.persistent = persistent
         _lib.check(_lib.load().batch_create(arr, n, fmt, flags, ctypes.byref(h)), "batch_create")
         self._h = h
         self.fmt = fmt

@@ -68,13 +68,17 @@ __global__ void __launch_bounds__(256)
     k_batch_zero(const ZeroChunk* __restrict__ chunks, int64_t n_chunks, double* const* values) {
     for (int64_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
         const ZeroChunk z = chunks[c];
-        double* p = values[z.mesh] + z.first;
+        double* p = global_ptr(values[z.mesh]) + z.first;
         for (int64_t i = threadIdx.x; i < z.count; i += blockDim.x) p[i] = 0.0;
     }
 }
 
-// Tiles of a path are split into kXcds contiguous ranges, one counter each.
+// Tiles of a path are split into kXcds contiguous ranges, one counter each;
+// the counters sit kCounterStride words apart (256 bytes), so that the eight
+// of one launch are eight separate memory-side atomic streams rather than
+// one hot line.
 constexpr int kXcds = 8;
+constexpr int kCounterStride = 32;
 
 __global__ void k_batch_reset(unsigned long long* counters, int32_t n) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) counters[i] = 0ull;
@@ -86,15 +90,76 @@ __device__ inline int64_t uniform64(int64_t v) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// One persistent kernel per code path.  The path's tile list is split into
-// one contiguous range per XCD (hardware dispatches workgroup b to XCD
-// b % 8); a block pops `chunk` tiles at a time from its XCD's range, so
-// neighbouring tiles -- which read the same element matrices -- run on one
-// XCD and share its L2, as the single-mesh kernels' block order arranges;
-// when its range is exhausted it helps the other ranges, and leaves when
-// every range is.  The tile entry is wave-uniform, so the mesh's arguments
-// come through the scalar cache into scalar registers, as a kernel argument
-// would; the next tile's entry is loaded while the current one is assembled.
+// One work tile of a batch.  The tile entry and the mesh's arguments are
+// wave-uniform scalar loads.  LOOP: the caller runs tiles one after another
+// in a loop, where the pipelined row kernel recomputes its per-lane index
+// arithmetic instead of keeping it live across tiles.
+template <int FMT, int PATH, bool LOOP>
+__device__ inline void batch_tile(const MeshDesc* __restrict__ meshes,
+                                  const double* const* __restrict__ ke,
+                                  double* const* __restrict__ values,
+                                  const BatchTile* __restrict__ tile, double* lds) {
+    const int32_t cur = ldc(&tile->mesh);
+    const int32_t colour = ldc(&tile->colour);
+    const int64_t index = ldc(&tile->index);
+    if (PATH <= kPipe24) {
+        OwnArgs O = meshes[cur].own_args;
+        O.ke = ke[cur];
+        O.values = values[cur];
+        to_global(O);
+        if (PATH == kOwnG4) owner_tiles<FMT, 4, 1, 8>(O, index, index + 1, lds);
+        if (PATH == kOwnG8) owner_tiles<FMT, 8, 1, 8>(O, index, index + 1, lds);
+        if (PATH == kOwnG16) owner_tiles<FMT, 16, 1, 8>(O, index, index + 1, lds);
+        if (PATH == kOwnG32) owner_tiles<FMT, 32, 1, 8>(O, index, index + 1, lds);
+        if (PATH == kOwnG64J1) owner_tiles<FMT, 64, 1, 8>(O, index, index + 1, lds);
+        if (PATH == kOwnG64J2) owner_tiles<FMT, 64, 2, 8>(O, index, index + 1, lds);
+        if (PATH == kOwnG64J4) owner_tiles<FMT, 64, 4, 4>(O, index, index + 1, lds);
+        if (PATH == kOwnG64J8) owner_tiles<FMT, 64, 8, 2>(O, index, index + 1, lds);
+        if (PATH == kOwnG64J16) owner_tiles<FMT, 64, 16, 1>(O, index, index + 1, lds);
+        if (PATH == kRows2J1) owner_rows_tile<FMT, 2, 1, 8>(O, index, lds);
+        if (PATH == kRows2J2) owner_rows_tile<FMT, 2, 2, 8>(O, index, lds);
+        if (PATH == kPipe24) owner_pipe_row<FMT, 3, 24, 8, 0, LOOP>(O, index, lds);
+    } else {
+        AsmArgs A = meshes[cur].asm_args;
+        A.ke = ke[cur];
+        A.values = values[cur];
+        if (colour >= 0) {
+            const int64_t* cp = meshes[cur].colour_ptr;
+            const int64_t c0 = ldc(cp + colour);
+            const int64_t c1 = ldc(cp + colour + 1);
+            A.elem_list = A.elem_list + c0;
+            A.count = c1 - c0;
+        }
+        to_global(A);
+        int32_t* li = reinterpret_cast<int32_t*>(lds);
+        if (PATH == kElemA16) elem_tile<FMT, true, 16, 1, 64>(A, index, li);
+        if (PATH == kElemA32) elem_tile<FMT, true, 32, 2, 64>(A, index, li);
+        if (PATH == kElemA64) elem_tile<FMT, true, 64, 16, 64>(A, index, li);
+        if (PATH == kElemP16) elem_tile<FMT, false, 16, 1, 64>(A, index, li);
+        if (PATH == kElemP32) elem_tile<FMT, false, 32, 2, 64>(A, index, li);
+        if (PATH == kElemP64) elem_tile<FMT, false, 64, 16, 64>(A, index, li);
+    }
+}
+
+// Tile-grid launch (the default): one workgroup per tile of a code path,
+// tiles first .. first + gridDim.x - 1, scheduled by the hardware dispatcher
+// as a single-mesh launch is.
+template <int FMT, int PATH>
+__global__ void __launch_bounds__(64)
+    k_batch_grid(const MeshDesc* __restrict__ meshes, const double* const* __restrict__ ke,
+                 double* const* __restrict__ values, const BatchTile* __restrict__ tiles,
+                 int64_t first) {
+    extern __shared__ double lds[];
+    batch_tile<FMT, PATH, false>(meshes, ke, values, tiles + first + blockIdx.x, lds);
+}
+
+// Persistent launch: as many workgroups as are resident at once.  The
+// path's tile list is split into one contiguous range per XCD (hardware
+// dispatches workgroup b to XCD b % 8); a workgroup pops `chunk` tiles at a
+// time from its XCD's range, so neighbouring tiles -- which read the same
+// connectivity rows and element matrices -- run on one XCD and share its
+// L2; when its range is exhausted it helps the other ranges, and leaves when
+// every range is.
 template <int FMT, int PATH>
 __global__ void __launch_bounds__(64)
     k_batch(const MeshDesc* __restrict__ meshes, const double* const* __restrict__ ke,
@@ -102,63 +167,21 @@ __global__ void __launch_bounds__(64)
             int64_t n_tiles, int64_t chunk, unsigned long long* counters) {
     extern __shared__ double lds[];
     __shared__ int64_t s_first;
-    constexpr bool kOwn = PATH <= kPipe24;
     const int home = (int)(blockIdx.x % kXcds);
     for (int step = 0; step < kXcds; ++step) {
         const int x = (home + step) % kXcds;
         const int64_t lo = n_tiles * x / kXcds, hi = n_tiles * (x + 1) / kXcds;
         for (;;) {
             if (threadIdx.x == 0)
-                s_first = lo + (int64_t)atomicAdd(counters + x, (unsigned long long)chunk);
+                s_first = lo + (int64_t)atomicAdd(counters + x * kCounterStride,
+                                                  (unsigned long long)chunk);
             __syncthreads();
             const int64_t first = uniform64(s_first);
             __syncthreads();
             if (first >= hi) break;
             const int64_t last = first + chunk < hi ? first + chunk : hi;
-            BatchTile next = tiles[first];
             for (int64_t t = first; t < last; ++t) {
-                // every lane read the same entry: tell the compiler, so that the
-                // mesh's arguments are scalar loads and stay in scalar registers
-                BatchTile T;
-                T.mesh = __builtin_amdgcn_readfirstlane(next.mesh);
-                T.colour = __builtin_amdgcn_readfirstlane(next.colour);
-                T.index = uniform64(next.index);
-                if (t + 1 < last) next = tiles[t + 1];
-                const int32_t cur = T.mesh;
-                if (kOwn) {
-                    OwnArgs O = meshes[cur].own_args;
-                    O.ke = ke[cur];
-                    O.values = values[cur];
-                    if (PATH == kOwnG4) owner_tiles<FMT, 4, 1, 8>(O, T.index, T.index + 1, lds);
-                    if (PATH == kOwnG8) owner_tiles<FMT, 8, 1, 8>(O, T.index, T.index + 1, lds);
-                    if (PATH == kOwnG16) owner_tiles<FMT, 16, 1, 8>(O, T.index, T.index + 1, lds);
-                    if (PATH == kOwnG32) owner_tiles<FMT, 32, 1, 8>(O, T.index, T.index + 1, lds);
-                    if (PATH == kOwnG64J1) owner_tiles<FMT, 64, 1, 8>(O, T.index, T.index + 1, lds);
-                    if (PATH == kOwnG64J2) owner_tiles<FMT, 64, 2, 8>(O, T.index, T.index + 1, lds);
-                    if (PATH == kOwnG64J4) owner_tiles<FMT, 64, 4, 4>(O, T.index, T.index + 1, lds);
-                    if (PATH == kOwnG64J8) owner_tiles<FMT, 64, 8, 2>(O, T.index, T.index + 1, lds);
-                    if (PATH == kOwnG64J16) owner_tiles<FMT, 64, 16, 1>(O, T.index, T.index + 1, lds);
-                    if (PATH == kRows2J1) owner_rows_tile<FMT, 2, 1, 8>(O, T.index, lds);
-                    if (PATH == kRows2J2) owner_rows_tile<FMT, 2, 2, 8>(O, T.index, lds);
-                    if (PATH == kPipe24) owner_pipe_row<FMT, 3, 24, 8, 0>(O, T.index, lds);
-                } else {
-                    AsmArgs A = meshes[cur].asm_args;
-                    A.ke = ke[cur];
-                    A.values = values[cur];
-                    if (T.colour >= 0) {
-                        const int64_t c0 = meshes[cur].colour_ptr[T.colour];
-                        const int64_t c1 = meshes[cur].colour_ptr[T.colour + 1];
-                        A.elem_list = A.elem_list + c0;
-                        A.count = c1 - c0;
-                    }
-                    int32_t* li = reinterpret_cast<int32_t*>(lds);
-                    if (PATH == kElemA16) elem_tile<FMT, true, 16, 1, 64>(A, T.index, li);
-                    if (PATH == kElemA32) elem_tile<FMT, true, 32, 2, 64>(A, T.index, li);
-                    if (PATH == kElemA64) elem_tile<FMT, true, 64, 16, 64>(A, T.index, li);
-                    if (PATH == kElemP16) elem_tile<FMT, false, 16, 1, 64>(A, T.index, li);
-                    if (PATH == kElemP32) elem_tile<FMT, false, 32, 2, 64>(A, T.index, li);
-                    if (PATH == kElemP64) elem_tile<FMT, false, 64, 16, 64>(A, T.index, li);
-                }
+                batch_tile<FMT, PATH, true>(meshes, ke, values, tiles + t, lds);
                 __syncthreads();  // LDS is reused by the next tile
             }
         }
@@ -167,10 +190,17 @@ __global__ void __launch_bounds__(64)
 
 using BatchKernel = void (*)(const MeshDesc*, const double* const*, double* const*,
                              const BatchTile*, int64_t, int64_t, unsigned long long*);
+using GridKernel = void (*)(const MeshDesc*, const double* const*, double* const*,
+                            const BatchTile*, int64_t);
 
 template <int FMT, int... P>
 constexpr std::array<BatchKernel, sizeof...(P)> kernel_table(std::integer_sequence<int, P...>) {
     return {&k_batch<FMT, P>...};
+}
+
+template <int FMT, int... P>
+constexpr std::array<GridKernel, sizeof...(P)> grid_table(std::integer_sequence<int, P...>) {
+    return {&k_batch_grid<FMT, P>...};
 }
 
 BatchKernel batch_kernel(int fmt, int path) {
@@ -178,6 +208,16 @@ BatchKernel batch_kernel(int fmt, int path) {
     static const auto t1 = kernel_table<1>(std::make_integer_sequence<int, kNumPaths>{});
     return fmt == 0 ? t0[path] : t1[path];
 }
+
+GridKernel grid_kernel(int fmt, int path) {
+    static const auto t0 = grid_table<0>(std::make_integer_sequence<int, kNumPaths>{});
+    static const auto t1 = grid_table<1>(std::make_integer_sequence<int, kNumPaths>{});
+    return fmt == 0 ? t0[path] : t1[path];
+}
+
+// Largest tile-grid launch: 64 lanes per workgroup keep the work-item count
+// of one dispatch within 32 bits; longer tile lists take several launches.
+constexpr int64_t kGridTilesMax = int64_t(1) << 24;
 
 }  // namespace
 }  // namespace feasm
@@ -208,6 +248,7 @@ struct feasm_batch {
     int device = 0;
     int accumulate = 0;
     int per_mesh_graph = 0;  // mode: every mesh's own kernels in one graph
+    int persistent = 0;      // mode: persistent launches pulling tiles from counters
     std::vector<const feasm_pattern*> patterns;
     feasm::MeshDesc* d_meshes = nullptr;
     std::vector<int64_t*> d_colour_ptrs;
@@ -220,8 +261,9 @@ struct feasm_batch {
     double** d_values = nullptr;
     std::vector<const double*> h_ke;  // last uploaded tables
     std::vector<double*> h_values;
-    hipStream_t streams[3] = {nullptr, nullptr, nullptr};  // capture only
-    hipEvent_t events[3] = {nullptr, nullptr, nullptr};
+    static constexpr int kStreams = 3;  // capture origin, phase 0, colours
+    hipStream_t streams[kStreams] = {nullptr, nullptr, nullptr};  // capture only
+    hipEvent_t events[kStreams] = {nullptr, nullptr, nullptr};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<int32_t> paths;  // per mesh, for batch_info
@@ -299,42 +341,47 @@ int mesh_path(const feasm_pattern* p, int fmt, int strategy, MeshDesc& D, size_t
     return FEASM_OK;
 }
 
+// Launches of phase 0 (row-owned and atomic meshes) run one after another on
+// one graph branch, largest work first (two alternating branches measured no
+// faster); colour phases are chained on a second branch beside them.
 int build_graph(feasm_batch* b) {
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < feasm_batch::kStreams; ++i) {
         FEASM_HIP(hipStreamCreateWithFlags(&b->streams[i], hipStreamNonBlocking));
         FEASM_HIP(hipEventCreateWithFlags(&b->events[i], hipEventDisableTiming));
     }
-    hipStream_t s0 = b->streams[0], s1 = b->streams[1], s2 = b->streams[2];
+    hipStream_t s0 = b->streams[0];
     FEASM_HIP(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
     const int32_t nl = (int32_t)b->launches.size();
-    k_batch_reset<<<1, 256, 0, s0>>>(b->d_counters, nl * kXcds);
+    if (b->persistent) k_batch_reset<<<1, 256, 0, s0>>>(b->d_counters, nl * kXcds * kCounterStride);
     if (b->n_zero > 0 && !b->accumulate)
         k_batch_zero<<<(unsigned)std::min<int64_t>(b->n_zero, 8192), 256, 0, s0>>>(b->d_zero, b->n_zero,
                                                                                   b->d_values);
     hipError_t err = hipEventRecord(b->events[0], s0);
-    // branch 1: phase 0, largest work first; branch 2: colour phases in order
-    bool used[3] = {true, false, false};
-    for (int br = 1; br <= 2 && err == hipSuccess; ++br) {
-        hipStream_t s = br == 1 ? s1 : s2;
-        bool any = false;
-        for (int32_t i = 0; i < nl; ++i) {
-            const Launch& L = b->launches[i];
-            if ((br == 1) != (L.phase == 0)) continue;
-            if (!any) {
-                err = hipStreamWaitEvent(s, b->events[0], 0);
-                any = true;
-            }
-            batch_kernel(b->fmt, L.path)<<<(unsigned)L.grid, 64, L.lds, s>>>(
-                b->d_meshes, b->d_ke, b->d_values, L.d_tiles, L.n_tiles, L.chunk,
-                b->d_counters + (int64_t)i * kXcds);
-        }
-        if (any && err == hipSuccess) {
-            err = hipEventRecord(b->events[br], s);
-            if (err == hipSuccess) err = hipStreamWaitEvent(s0, b->events[br], 0);
+    bool used[feasm_batch::kStreams] = {true, false, false};
+    for (int32_t i = 0; i < nl && err == hipSuccess; ++i) {
+        const Launch& L = b->launches[i];
+        const int br = L.phase == 0 ? 1 : 2;
+        hipStream_t s = b->streams[br];
+        if (!used[br]) {
+            err = hipStreamWaitEvent(s, b->events[0], 0);
             used[br] = true;
         }
+        if (b->persistent) {
+            batch_kernel(b->fmt, L.path)<<<(unsigned)L.grid, 64, L.lds, s>>>(
+                b->d_meshes, b->d_ke, b->d_values, L.d_tiles, L.n_tiles, L.chunk,
+                b->d_counters + (int64_t)i * kXcds * kCounterStride);
+        } else {
+            for (int64_t f = 0; f < L.n_tiles; f += kGridTilesMax)
+                grid_kernel(b->fmt, L.path)<<<(unsigned)std::min(kGridTilesMax, L.n_tiles - f), 64,
+                                              L.lds, s>>>(b->d_meshes, b->d_ke, b->d_values,
+                                                          L.d_tiles, f);
+        }
     }
-    (void)used;
+    for (int br = 1; br < feasm_batch::kStreams && err == hipSuccess; ++br) {
+        if (!used[br]) continue;
+        err = hipEventRecord(b->events[br], b->streams[br]);
+        if (err == hipSuccess) err = hipStreamWaitEvent(s0, b->events[br], 0);
+    }
     const hipError_t le = hipGetLastError();
     const hipError_t ce = hipStreamEndCapture(s0, &b->graph);
     FEASM_HIP(err);
@@ -398,7 +445,7 @@ void release_batch(feasm_batch* b) {
     }
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < feasm_batch::kStreams; ++i) {
         if (b->streams[i]) (void)hipStreamDestroy(b->streams[i]);
         if (b->events[i]) (void)hipEventDestroy(b->events[i]);
     }
@@ -549,8 +596,15 @@ int create(feasm_batch* b, const feasm_pattern* const* patterns, int64_t count, 
             (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel(fmt, path), 64,
                                                                L.lds);
             const int64_t cap = (int64_t)cus * std::max(per_cu, 1);
-            L.chunk = std::max<int64_t>(1, std::min<int64_t>(32, L.n_tiles / (cap * 8)));
-            L.grid = std::max<int64_t>(1, std::min<int64_t>(cap, ceil_div(L.n_tiles, L.chunk)));
+            if (b->persistent) {
+                // small chunks keep the in-flight rows of an XCD close together;
+                // four tiles per counter pop measured best on the 512-mesh mix
+                L.chunk = std::max<int64_t>(1, std::min<int64_t>(4, L.n_tiles / (cap * 8)));
+                L.grid = std::max<int64_t>(1, std::min<int64_t>(cap, ceil_div(L.n_tiles, L.chunk)));
+            } else {
+                L.chunk = 1;
+                L.grid = std::min(L.n_tiles, kGridTilesMax);
+            }
             {
             const int rc__ = dev_alloc(b->alloc, (void**)&L.d_tiles, sizeof(BatchTile) * tl.size(), nullptr, "batch_create");
             if (rc__ != FEASM_OK) return rc__;
@@ -564,7 +618,8 @@ int create(feasm_batch* b, const feasm_pattern* const* patterns, int64_t count, 
         b->launches.insert(b->launches.end(), here.begin(), here.end());
     }
     {
-        const int rc = dev_alloc_n(b->alloc, &b->d_counters, (int64_t)b->launches.size() * kXcds, nullptr,
+        const int rc = dev_alloc_n(b->alloc, &b->d_counters,
+                                   (int64_t)b->launches.size() * kXcds * kCounterStride, nullptr,
                                    "batch_create");
         if (rc != FEASM_OK) return rc;
     }
@@ -607,11 +662,14 @@ extern "C" int batch_create(const feasm_pattern* const* patterns, int64_t count,
         if (count > INT32_MAX) FEASM_FAIL(FEASM_EOVERFLOW, "batch_create: too many meshes");
         if (fmt != FEASM_FMT_CSR && fmt != FEASM_FMT_CRAC)
             FEASM_FAIL(FEASM_EINVAL, "batch_create: fmt must be FEASM_FMT_CSR or FEASM_FMT_CRAC");
-        if (flags & ~(uint32_t)(FEASM_ACCUMULATE | FEASM_BATCH_PER_MESH_GRAPH))
+        if (flags & ~(uint32_t)(FEASM_ACCUMULATE | FEASM_BATCH_PER_MESH_GRAPH | FEASM_BATCH_PERSISTENT))
             FEASM_FAIL(FEASM_EINVAL, "batch_create: unknown flag");
+        if ((flags & FEASM_BATCH_PER_MESH_GRAPH) && (flags & FEASM_BATCH_PERSISTENT))
+            FEASM_FAIL(FEASM_EINVAL, "batch_create: per-mesh-graph and persistent modes exclude each other");
         feasm_batch* b = new (std::nothrow) feasm_batch();
         if (!b) FEASM_FAIL(FEASM_ENOMEM, "batch_create: out of host memory");
         b->per_mesh_graph = (flags & FEASM_BATCH_PER_MESH_GRAPH) ? 1 : 0;
+        b->persistent = (flags & FEASM_BATCH_PERSISTENT) ? 1 : 0;
         const int rc = create(b, patterns, count, fmt, (flags & FEASM_ACCUMULATE) ? 1 : 0);
         if (rc != FEASM_OK) {
             (void)hipDeviceSynchronize();

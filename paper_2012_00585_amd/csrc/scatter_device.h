@@ -230,6 +230,57 @@ struct OwnArgs {
     const int32_t* node_list;  // optional: block i owns node node_list[i]
 };
 
+// A pointer read from memory (a batch's table of meshes) is generic to the
+// compiler, which then accesses it with flat instructions: 64-bit addresses
+// in vector registers and waits that also count LDS operations.  Rebuilding
+// it from its integer value as a global-address-space pointer gives global
+// loads and stores, as for a pointer passed as a kernel argument.
+template <class T>
+__device__ inline T* global_ptr(T* p) {
+    using G = __attribute__((address_space(1))) T*;
+    return (T*)(G)(uintptr_t)p;
+}
+
+__device__ inline void to_global(OwnArgs& A) {
+    A.conn = global_ptr(A.conn);
+    A.inc_ptr = global_ptr(A.inc_ptr);
+    A.inc_q = global_ptr(A.inc_q);
+    A.inc_elem = global_ptr(A.inc_elem);
+    A.inc_local = global_ptr(A.inc_local);
+    A.row_ptr = global_ptr(A.row_ptr);
+    A.col_idx = global_ptr(A.col_idx);
+    A.crac_row_ptr = global_ptr(A.crac_row_ptr);
+    A.ca = global_ptr(A.ca);
+    A.ke = global_ptr(A.ke);
+    A.values = global_ptr(A.values);
+    A.node_ptr = global_ptr(A.node_ptr);
+    A.map = global_ptr(A.map);
+    A.node_list = global_ptr(A.node_list);
+}
+
+// A load from a pattern array, which no kernel here writes while reading
+// it: through the constant address space, a wave-uniform address becomes a
+// scalar load even after the kernel's own stores (in a loop over rows the
+// compiler cannot tell on its own that those stores miss the pattern).
+template <class T>
+__device__ inline T ldc(const T* p) {
+    using C = const __attribute__((address_space(4))) T*;
+    return *(C)(uintptr_t)p;
+}
+
+__device__ inline void to_global(AsmArgs& A) {
+    A.conn = global_ptr(A.conn);
+    A.row_ptr = global_ptr(A.row_ptr);
+    A.col_idx = global_ptr(A.col_idx);
+    A.crac_row_ptr = global_ptr(A.crac_row_ptr);
+    A.ca = global_ptr(A.ca);
+    A.ke = global_ptr(A.ke);
+    A.values = global_ptr(A.values);
+    A.elem_list = global_ptr(A.elem_list);
+    A.cache = global_ptr(A.cache);
+    A.cache_out = global_ptr(A.cache_out);
+}
+
 template <int FMT>
 __device__ inline int32_t row_lookup(const int32_t* sidx, int32_t ncols, int32_t npairs, int32_t rs,
                                      int32_t col) {
@@ -314,12 +365,12 @@ __device__ inline void owner_tiles(const OwnArgs& A, int64_t first, int64_t last
         int64_t ib = 0;
         if (active) {
             const int32_t R = d * (int32_t)v;
-            ib = A.inc_ptr[v];
-            L = (int32_t)(A.inc_ptr[v + 1] - ib);
+            ib = ldc(A.inc_ptr + v);
+            L = (int32_t)(ldc(A.inc_ptr + v + 1) - ib);
             if (FMT == kMap) {
-                const int64_t nb = A.node_ptr[v];
+                const int64_t nb = ldc(A.node_ptr + v);
                 rs = (int32_t)((int64_t)d * d * nb);
-                ncols = (int32_t)(d * (A.node_ptr[v + 1] - nb));
+                ncols = (int32_t)(d * (ldc(A.node_ptr + v + 1) - nb));
             } else if (FMT == kCSR) {
                 rs = A.row_ptr[R];
                 ncols = A.row_ptr[R + 1] - rs;
@@ -610,7 +661,7 @@ __device__ inline void pipe_issue(const OwnArgs& A, int64_t tbeg, int64_t T, int
     const int l = OPAQUE ? opaque_lane() : (int)threadIdx.x;
     int32_t qs[B];
 #pragma unroll
-    for (int tb = 0; tb < B; ++tb) qs[tb] = A.inc_q[tbeg + t0 + tb];
+    for (int tb = 0; tb < B; ++tb) qs[tb] = ldc(A.inc_q + tbeg + t0 + tb);
     // index loads first: their waits then leave the element rows in flight
 #pragma unroll
     for (int i = 0; i < W; ++i) {
@@ -676,38 +727,41 @@ __device__ inline void pipe_consume(const OwnArgs& A, int64_t T, int64_t t0, int
 
 // MODE 0: every row has at most B entries (one batch, no loop); 1: batches
 // one after another; 2: the next batch is issued before the current one is
-// added (two batches of registers).
-template <int FMT, int D, int N, int B, int MODE>
+// added (two batches of registers).  OPQ: per-lane index arithmetic is
+// recomputed where it is used rather than hoisted out of the loops and kept
+// live (the batch loops, and MODE 1 and 2, would otherwise hold it in
+// registers across every row).
+template <int FMT, int D, int N, int B, int MODE, bool OPQ = (MODE != 0)>
 __device__ inline void owner_pipe_row(const OwnArgs& A, int64_t v, double* lds_d) {
     static_assert(D * N >= 64 && N % D == 0 && B <= kIncPad, "pipelined rows need D*N >= 64");
     using P = PipeBatch<FMT, D, N, B>;
-    // in loops, per-lane index arithmetic is recomputed rather than kept live
-    constexpr bool OPQ = MODE != 0;
     constexpr int SI = 4;  // index words per lane staged ahead of the first batch
-    const int l = threadIdx.x;
+    // the row set-up's lane arithmetic too, in a one-batch row inside a
+    // caller's loop (MODE 1 and 2 take more registers that way)
+    const int l = (OPQ && MODE == 0) ? opaque_lane() : (int)threadIdx.x;
     double* acc = lds_d;
     int32_t* sidx = reinterpret_cast<int32_t*>(acc + A.acc_doubles);
     int32_t* scol0 = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(lds_d) + A.group_bytes);
     int32_t* scol1 = scol0 + P::KB;
 
-    const int64_t tbeg = A.inc_ptr[v], T = A.inc_ptr[v + 1] - tbeg;
+    const int64_t tbeg = ldc(A.inc_ptr + v), T = ldc(A.inc_ptr + v + 1) - tbeg;
     const int32_t Rw = D * (int32_t)v;
     int32_t rs = 0, ncols = 0, npairs = 0, nidx = 0;
     const int32_t* isrc = nullptr;
     if (FMT == kMap) {
-        const int64_t nb = A.node_ptr[v];
+        const int64_t nb = ldc(A.node_ptr + v);
         rs = (int32_t)((int64_t)D * D * nb);
-        ncols = (int32_t)(D * (A.node_ptr[v + 1] - nb));
+        ncols = (int32_t)(D * (ldc(A.node_ptr + v + 1) - nb));
     } else if (FMT == kCSR) {
-        rs = A.row_ptr[Rw];
-        ncols = A.row_ptr[Rw + 1] - rs;
+        rs = ldc(A.row_ptr + Rw);
+        ncols = ldc(A.row_ptr + Rw + 1) - rs;
         isrc = A.col_idx + rs;
         nidx = ncols;
     } else {
-        const int32_t pb = A.crac_row_ptr[Rw], pe = A.crac_row_ptr[Rw + 1];
+        const int32_t pb = ldc(A.crac_row_ptr + Rw), pe = ldc(A.crac_row_ptr + Rw + 1);
         npairs = (pe - pb) >> 1;
-        rs = npairs > 0 ? A.ca[pb + 1] : 0;
-        ncols = npairs > 0 ? A.ca[pe + 1] - rs : 0;
+        rs = npairs > 0 ? ldc(A.ca + pb + 1) : 0;
+        ncols = npairs > 0 ? ldc(A.ca + pe + 1) - rs : 0;
         isrc = A.ca + pb;
         nidx = npairs > 0 ? 2 * npairs + 2 : 0;
     }

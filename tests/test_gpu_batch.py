@@ -57,6 +57,10 @@ def _mix():
     ]
 
 
+# batch modes: one launch per path with a workgroup per tile (default),
+# persistent launches, every mesh's own kernels
+MODES = {"grid": {}, "persistent": {"persistent": True}, "per_mesh_graph": {"per_mesh_graph": True}}
+
 STRATS = {
     "owner": (3, 0),
     "atomic16": (1, 16),
@@ -68,8 +72,8 @@ STRATS = {
 
 @pytest.mark.parametrize("fmt", [0, 1])
 @pytest.mark.parametrize("assign", ["owner", "mixed"])
-@pytest.mark.parametrize("per_mesh_graph", [False, True])
-def test_batch_matches_oracle(feasm, orc, fmt, assign, per_mesh_graph):
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_matches_oracle(feasm, orc, fmt, assign, mode):
     from paper_2012_00585_amd.batch import Batch
 
     dev = torch.device("cuda:0")
@@ -92,9 +96,9 @@ def test_batch_matches_oracle(feasm, orc, fmt, assign, per_mesh_graph):
         kes.append(torch.from_numpy(ke).to(dev))
         vals.append(torch.full((p.nnz,), np.nan, dtype=torch.float64, device=dev))
         refs.append((name, strat, ov, oa))
-    b = Batch(pats, fmt=fmt, per_mesh_graph=per_mesh_graph)
+    b = Batch(pats, fmt=fmt, **MODES[mode])
     info = b.info()
-    say(f"[batch] fmt={fmt} assign={assign} per_mesh_graph={per_mesh_graph} {info}")
+    say(f"[batch] fmt={fmt} assign={assign} mode={mode} {info}")
     for rep in range(3):
         if rep == 2:  # new buffers: the pointer table is refreshed
             kes = [k.clone() for k in kes]
@@ -136,10 +140,10 @@ def test_batch_accumulate_and_integer_exact(feasm, orc):
         kes.append(torch.from_numpy(ke).to(dev))
         vals.append(torch.full((p.nnz,), 5.0, dtype=torch.float64, device=dev))
         refs.append(ov)
-    for per_mesh_graph in (False, True):
+    for mode in MODES:
         for v in vals:
             v.fill_(5.0)
-        b = Batch(pats, fmt=1, accumulate=True, per_mesh_graph=per_mesh_graph)
+        b = Batch(pats, fmt=1, accumulate=True, **MODES[mode])
         b.assemble(kes, vals)
         for v, ov in zip(vals, refs):
             assert (_np(v) == ov + 5.0).all()
@@ -216,7 +220,8 @@ _MIX_REFS = {}
 @pytest.mark.parametrize("fmt", [1, 0], ids=["crac", "csr"])
 def test_batch512_full_mix(feasm, orc, fmt):
     """The full 512-mesh mix in the launch configurations the benchmark
-    times (autotuned handles; persistent and per-mesh-graph batches), with
+    times (autotuned handles; tile-grid, persistent and per-mesh-graph
+    batches), with
     element matrices from the device generator.
     * every mesh: nnz equals the structured closed form, no value is left
       unwritten, and the row-sum and total invariants hold;
@@ -246,11 +251,11 @@ def test_batch512_full_mix(feasm, orc, fmt):
     autotune.autotune(pats, kes, vals, fmt, reps=2, warmup=1, log=say)
     paths = None
     refs = _MIX_REFS
-    for per_mesh_graph in (False, True):
-        say(f"[batch512] fmt={fmt} per_mesh_graph={per_mesh_graph}")
+    for mode in MODES:
+        say(f"[batch512] fmt={fmt} mode={mode}")
         for v in vals:
             v.fill_(np.nan)
-        b = Batch(pats, fmt=fmt, per_mesh_graph=per_mesh_graph)
+        b = Batch(pats, fmt=fmt, **MODES[mode])
         if paths is None:
             paths = b.info()["paths"]
             groups = {}
@@ -277,7 +282,7 @@ def test_batch512_full_mix(feasm, orc, fmt):
             got = _np(vals[i])
             ov, oa = refs[i]
             if paths[i].startswith(("own", "rows")):  # row-owned: element order
-                assert (got == ov).all(), (i, specs[i], paths[i], per_mesh_graph)
+                assert (got == ov).all(), (i, specs[i], paths[i], mode)
             else:
                 assert_values_close(got, ov, oa, what=f"mesh {i} {specs[i]} {paths[i]}")
         b.free()
