@@ -243,6 +243,16 @@ def main():
         "csr_spin": lambda: feasm.assemble_csr(p, ke_d, values, S | ACC),
         "crac_spin": lambda: feasm.assemble_crac(p, ke_d, values, S | ACC),
     }
+    p_r = None
+    if args.workload == "tet40":
+        # scattered node numbering: the row-owned lookup record built with the
+        # pattern (on grid-numbered meshes it only adds reads; the hex64
+        # re-assembly figures, which use the same record, show that)
+        p_r = feasm.pattern_build(conn_d, w.dofs_per_node, w.n_nodes,
+                                  feasm.BUILD_CSR | feasm.BUILD_CRAC | feasm.BUILD_OWNER_MAP)
+        for name, fn in (("csr_owner_record", feasm.assemble_csr),
+                         ("crac_owner_record", feasm.assemble_crac)):
+            full[name] = scatter_only[name] = (lambda f=fn: f(p_r, ke_d, values, O))
     reps = max(args.steps, 5)
     variants = {}
     if args.only:
@@ -253,7 +263,7 @@ def main():
         t_full = stats(time_calls(fn, reps, args.warmup))
         t_sc = stats(time_calls(scatter_only[name], reps, args.warmup))
         fmt, strategy = name.split("_", 1)
-        nbytes = algorithmic_bytes(w, p, fmt, strategy)
+        nbytes = algorithmic_bytes(w, p, fmt, "record" if strategy == "owner_record" else strategy)
         variants[name] = {
             "assemble_ms": t_full,
             "scatter_only_ms": t_sc,
@@ -356,7 +366,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_source": os.path.relpath(prof, ROOT) if traffic else None,
-                     "kernel": (f"row-owned kernel ({best}, one launch)" if strategy == "owner" else
+                     "kernel": (f"row-owned kernels of one call ({best}; one launch, or two "
+                                f"where light and heavy rows are split)"
+                                if strategy.startswith("owner") else
                                 f"k_assemble ({best}, scatter only)"),
                      "bytes_per_launch": v["algorithmic_bytes"],
                      "kernel_ms": kernel_ms},
@@ -370,6 +382,8 @@ def main():
         line["cpu_baseline"] = cpu_baseline(w, ke, args.cpu_reps)
     p.free()
     p_t.free()
+    if p_r is not None:
+        p_r.free()
     del ke_d, values, ke
     if args.workload == "hex64":
         # the other workloads, compact, in the same line
@@ -403,22 +417,32 @@ def tet40_section(args):
     t0 = time.perf_counter()
     p = feasm.pattern_build(conn_d, w.dofs_per_node, w.n_nodes, feasm.BUILD_CSR | feasm.BUILD_CRAC)
     build_ms = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    p_rec = feasm.pattern_build(conn_d, w.dofs_per_node, w.n_nodes,
+                                feasm.BUILD_CSR | feasm.BUILD_CRAC | feasm.BUILD_OWNER_MAP)
+    build_rec_ms = (time.perf_counter() - t0) * 1e3
     ke_d = feasm.generate_ke(feasm.RECIPE_SPD, w.n_elem, w.n, 0)
     values = torch.zeros(p.nnz, dtype=torch.float64, device=dev)
     O, A, ACC = feasm.SCATTER_OWNER, feasm.SCATTER_ATOMIC, feasm.ACCUMULATE
     reps = max(args.steps, 5)
     out = {"workload": wdesc.replace("30x30 SPD FP64 Ke, seed 0",
                                      "30x30 SPD FP64 Ke from the device generator, key 0"),
-           "n_elem": w.n_elem, "nnz": p.nnz, "n_ca": p.n_ca, "pattern_build_ms": build_ms}
-    for name, fn, sc in (("crac_owner", feasm.assemble_crac, O), ("csr_owner", feasm.assemble_csr, O),
-                         ("crac_atomic", feasm.assemble_crac, A),
-                         ("csr_atomic", feasm.assemble_csr, A)):
-        full = stats(time_calls(lambda f=fn, c=sc: f(p, ke_d, values, c), reps, args.warmup))
+           "n_elem": w.n_elem, "nnz": p.nnz, "n_ca": p.n_ca, "pattern_build_ms": build_ms,
+           "pattern_build_with_record_ms": build_rec_ms}
+    for name, q, fn, sc in (("crac_owner", p, feasm.assemble_crac, O),
+                            ("csr_owner", p, feasm.assemble_csr, O),
+                            ("crac_owner_record", p_rec, feasm.assemble_crac, O),
+                            ("csr_owner_record", p_rec, feasm.assemble_csr, O),
+                            ("crac_atomic", p, feasm.assemble_crac, A),
+                            ("csr_atomic", p, feasm.assemble_csr, A)):
+        full = stats(time_calls(lambda f=fn, c=sc, q=q: f(q, ke_d, values, c), reps, args.warmup))
         # the row-owned strategy writes every value once and has no reset
         # pass: its full assembly is its scatter
         sco = full if sc == O else stats(time_calls(lambda f=fn, c=sc: f(p, ke_d, values, c | ACC),
                                                     reps, args.warmup))
-        fmt, strategy = name.split("_")
+        fmt, strategy = name.split("_")[:2]
+        if name.endswith("_record"):
+            strategy = "record"  # the record replaces conn and the row index words
         nb = algorithmic_bytes(w, p, fmt, strategy)
         out[name] = {"assemble_ms": full["mean"], "scatter_only_ms": sco["mean"],
                      "algorithmic_bytes": nb,
@@ -426,11 +450,14 @@ def tet40_section(args):
                      "roofline_frac": nb / (sco["mean"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
         log(f"[bench]   tet40 {name}: {full['mean']:.3f} ms (scatter only {sco['mean']:.3f} ms, "
             f"{out[name]['roofline_frac']:.2f} of HBM peak)")
-    best = min(("crac_owner", "csr_owner"), key=lambda k: out[k]["assemble_ms"])
+    best = min(("crac_owner", "csr_owner", "crac_owner_record", "csr_owner_record"),
+               key=lambda k: out[k]["assemble_ms"])
     out["step_variant"] = best
     out["step_ms"] = out[best]["assemble_ms"]
+    out["step_roofline_frac"] = out[best]["roofline_frac"]
     out["elements_per_s"] = w.n_elem / (out["step_ms"] * 1e-3)
     p.free()
+    p_rec.free()
     return out
 
 

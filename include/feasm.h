@@ -68,7 +68,8 @@ enum {
     FEASM_BUILD_CSR = 1,    /* row_ptr[n_rows+1], col_idx[nnz] */
     FEASM_BUILD_CRAC = 2,   /* crac_row_ptr[n_rows+1], col_align[n_ca] */
     FEASM_BUILD_COLOUR = 4, /* element colouring for the atomic-free scatter */
-    FEASM_BUILD_TILES = 8   /* element tiles for the atomic scatter (see FEASM_SCATTER_ATOMIC) */
+    FEASM_BUILD_TILES = 8,  /* element tiles for the atomic scatter (see FEASM_SCATTER_ATOMIC) */
+    FEASM_BUILD_OWNER_MAP = 16 /* the row-owned lookup record, built with the pattern */
 };
 
 /* format selector for reassemble_values */
@@ -134,10 +135,22 @@ enum {
  * and mesh is accepted; elements whose tile has more distinct node pairs
  * than the accumulator holds fall back to one atomic per contribution.
  *
+ * Lookup record (FEASM_BUILD_OWNER_MAP): for every node, incident element
+ * and element node, the offset of that node's first column inside the
+ * owned row (int32, n_elem * k^2 entries, the same for both formats).  The
+ * row-owned strategy then reads it instead of the element's connectivity
+ * row and the search in the owned row, from the first assembly on (without
+ * the flag it is built by the first row-owned reassemble_values).  Pays on
+ * meshes whose node numbering is scattered (the permuted tet10 mesh); on a
+ * mesh numbered along a grid the connectivity rows are cache hits and the
+ * record only adds reads.
+ *
  * Errors: EINVAL for bad arguments; ERANGE if a node id is out of range
  * (checked on the device, reported before returning); EOVERFLOW for int32
  * overflow of the pattern; ELIMIT if a node is shared by so many elements
- * that its candidate column list exceeds 8192 entries; ENOMEM; EHIP.
+ * that its candidate column list exceeds 8192 entries, or (with
+ * FEASM_BUILD_OWNER_MAP) its row index words exceed 64 KiB of LDS; ENOMEM;
+ * EHIP.
  * Synchronises `stream` before returning, so no asynchronous error is lost.
  */
 int pattern_build(const int32_t* conn, int64_t n_elem, int32_t nodes_per_elem,

@@ -24,6 +24,7 @@ BUILD_CSR = 1
 BUILD_CRAC = 2
 BUILD_COLOUR = 4
 BUILD_TILES = 8
+BUILD_OWNER_MAP = 16
 FMT_CSR = 0
 FMT_CRAC = 1
 SCATTER_AUTO = 0

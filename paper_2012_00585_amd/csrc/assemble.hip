@@ -302,6 +302,11 @@ int launch_owner(const feasm_pattern* p, int fmt, const double* ke, double* valu
 }
 
 // Builds the row-owned lookup record of a handle (same for both formats).
+size_t owner_map_lds(const feasm_pattern* p) {
+    return sizeof(int32_t) *
+           (size_t)std::max<int64_t>((int64_t)p->d * p->max_deg, 2 * (int64_t)p->max_deg + 2);
+}
+
 int build_owner_map(feasm_pattern* p, int fmt, hipStream_t s) {
     OwnArgs A{};
     A.conn = p->conn;
@@ -315,8 +320,9 @@ int build_owner_map(feasm_pattern* p, int fmt, hipStream_t s) {
     A.crac_row_ptr = p->crac_row_ptr;
     A.ca = p->ca;
     A.n_nodes = p->n_nodes;
-    const size_t lds = sizeof(int32_t) * (size_t)std::max<int64_t>(
-        (int64_t)p->d * p->max_deg, 2 * (int64_t)p->max_deg + 2);
+    const size_t lds = owner_map_lds(p);
+    if (lds > 64 * 1024)
+        FEASM_FAIL(FEASM_ELIMIT, "row-owned lookup record: node rows too long for the LDS");
     const unsigned grid = (unsigned)std::min<int64_t>(p->n_nodes, 1 << 20);
     if (fmt == kCSR)
         k_owner_map<kCSR><<<grid, 64, lds, s>>>(A, p->owner_map);
@@ -388,8 +394,12 @@ int assemble_impl(const feasm_pattern* p, int fmt, const double* ke, double* val
     if (scatter != FEASM_SCATTER_ATOMIC && scatter != FEASM_SCATTER_COLOURED &&
         scatter != FEASM_SCATTER_OWNER && scatter != FEASM_SCATTER_SPIN)
         FEASM_FAIL(FEASM_EINVAL, std::string(who) + ": unknown scatter strategy");
-    if (scatter == FEASM_SCATTER_OWNER)
+    if (scatter == FEASM_SCATTER_OWNER) {
+        // a record built with the pattern replaces the connectivity reads and
+        // row searches of every row-owned call
+        if (!owner_map && (p->flags & FEASM_BUILD_OWNER_MAP)) owner_map = p->owner_map;
         return launch_owner(p, fmt, ke, values, accumulate, s, owner_map);
+    }
     if (scatter == FEASM_SCATTER_SPIN) {
         if (!accumulate) {
             k_zero<<<(unsigned)std::min<int64_t>(ceil_div(p->nnz / 2 + 1, 256), 16384), 256, 0, s>>>(
@@ -456,6 +466,13 @@ int assemble_impl(const feasm_pattern* p, int fmt, const double* ke, double* val
 int assemble_on_stream(const feasm_pattern* p, int fmt, const double* ke, double* values,
                        int scatter, hipStream_t s) {
     return assemble_impl(p, fmt, ke, values, scatter, nullptr, nullptr, s, "assemble_batch");
+}
+
+int build_owner_record(feasm_pattern* p, hipStream_t s) {
+    const int rc = dev_alloc_n(p->alloc, &p->owner_map, p->n_elem * p->k * p->k, s,
+                               "pattern_build (lookup record)");
+    if (rc != FEASM_OK) return rc;
+    return build_owner_map(p, (p->flags & FEASM_BUILD_CRAC) ? kCRAC : kCSR, s);
 }
 
 void release_owner_map(feasm_pattern* p) {

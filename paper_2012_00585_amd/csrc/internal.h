@@ -215,6 +215,8 @@ int assemble_on_stream(const feasm_pattern* p, int fmt, const double* ke, double
 void release_pattern(feasm_pattern* p);
 void release_cache(feasm_pattern* p);
 void release_owner_map(feasm_pattern* p);
+// The row-owned lookup record, built during pattern_build (asynchronous on s).
+int build_owner_record(feasm_pattern* p, hipStream_t s);
 
 // XCD-aware block order: hardware dispatches workgroup b to XCD b % 8.
 // Maps it to a logical index so that each XCD processes one contiguous range.

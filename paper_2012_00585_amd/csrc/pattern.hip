@@ -449,7 +449,9 @@ int build(feasm_pattern* p, const int32_t* conn_in, hipStream_t s) {
 
     if (p->flags & FEASM_BUILD_COLOUR) TRY(build_colouring(p, s));
     if (p->flags & FEASM_BUILD_TILES) TRY(build_tiles(p, s));
+    if (p->flags & FEASM_BUILD_OWNER_MAP) TRY(build_owner_record(p, s));
     FEASM_HIP(hipStreamSynchronize(s));
+    p->owner_map_valid = p->owner_map != nullptr;
     p->n_light = n_light;
     return FEASM_OK;
 }
@@ -482,7 +484,7 @@ extern "C" int pattern_build(const int32_t* conn, int64_t n_elem, int32_t nodes_
             FEASM_FAIL(FEASM_EINVAL, "pattern_build: n_elem, nodes_per_elem, dofs_per_node and "
                                      "n_nodes must be positive");
         if (build_flags & ~(uint32_t)(FEASM_BUILD_CSR | FEASM_BUILD_CRAC | FEASM_BUILD_COLOUR |
-                                      FEASM_BUILD_TILES))
+                                      FEASM_BUILD_TILES | FEASM_BUILD_OWNER_MAP))
             FEASM_FAIL(FEASM_EINVAL, "pattern_build: unknown build flag");
         if (!(build_flags & (FEASM_BUILD_CSR | FEASM_BUILD_CRAC)))
             FEASM_FAIL(FEASM_EINVAL, "pattern_build: request FEASM_BUILD_CSR and/or FEASM_BUILD_CRAC");

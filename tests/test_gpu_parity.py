@@ -256,6 +256,48 @@ def test_tet40_full(feasm, orc, tet40_ref):
         assert abs(v.sum() - ke.sum()) <= 1e-12 * np.abs(ke).sum() + 1e-12 * total
         del v
     p.free()
+    say("[parity] tet40 with the lookup record built with the pattern: every value")
+    p = feasm.pattern_build(torch.from_numpy(w.conn).to(dev), 3, w.n_nodes,
+                            feasm.BUILD_CSR | feasm.BUILD_CRAC | feasm.BUILD_OWNER_MAP)
+    for fn in (feasm.assemble_csr, feasm.assemble_crac):
+        assert (_np(fn(p, ke_d)) == r.ov).all(), fn.__name__
+    p.free()
+
+
+@pytest.mark.parametrize("name,make,d", CASES, ids=[c[0] for c in CASES])
+def test_owner_record_built_with_pattern(feasm, orc, name, make, d):
+    """FEASM_BUILD_OWNER_MAP: the row-owned calls read the lookup record from
+    the first assembly on; the same sums in the same element order, so the
+    values equal the oracle's bit for bit (a repeated node: within the
+    tolerance), for assembly, accumulation and re-assembly."""
+    conn, nn = make()
+    E, k = conn.shape
+    dev = torch.device("cuda:0")
+    p = feasm.pattern_build(torch.from_numpy(np.ascontiguousarray(conn, dtype=np.int32)).to(dev), d,
+                            nn, feasm.BUILD_CSR | feasm.BUILD_CRAC | feasm.BUILD_OWNER_MAP)
+    ke = matrices.ke_spd(E, k * d, seed=11)
+    rp, ci = orc.pattern(conn, d, nn)
+    ov, oa = orc.assemble(conn, d, ke, rp, ci)
+    ke_d = torch.from_numpy(ke).to(dev)
+    exact = name != "repeated_node"
+    say(f"[parity] lookup record built with the pattern: {name}")
+    for fmt, fn in ((feasm.FMT_CSR, feasm.assemble_csr), (feasm.FMT_CRAC, feasm.assemble_crac)):
+        try:
+            v = fn(p, ke_d, scatter=feasm.SCATTER_OWNER)
+        except feasm.FeasmError as e:  # rows longer than the LDS accumulator
+            assert "ELIMIT" in str(e)
+            continue
+        got = [("assemble", _np(v))]
+        fn(p, ke_d, values=v, scatter=feasm.SCATTER_OWNER | feasm.ACCUMULATE)
+        got.append(("accumulate", _np(v) / 2))
+        got.append(("reassemble", _np(feasm.reassemble_values(p, fmt, ke_d,
+                                                              scatter=feasm.SCATTER_OWNER))))
+        for what, g in got:
+            if exact:
+                assert (g == ov).all(), (name, fmt, what)
+            else:
+                assert_values_close(g, ov, oa, what=f"{name} {fmt} {what}")
+    p.free()
 
 
 def test_error_paths_on_device(feasm):
