@@ -549,9 +549,10 @@ int create(feasm_batch* b, const feasm_pattern* const* patterns, int64_t count, 
             A.elem_list = p->colour_elems;
             const int32_t nc = p->n_colours;
             {
-            const int rc__ = dev_alloc(b->alloc, (void**)&b->d_colour_ptrs[m], sizeof(int64_t) * (nc + 1), nullptr, "batch_create");
-            if (rc__ != FEASM_OK) return rc__;
-        }
+                const int rc__ = dev_alloc(b->alloc, (void**)&b->d_colour_ptrs[m],
+                                           sizeof(int64_t) * (nc + 1), nullptr, "batch_create");
+                if (rc__ != FEASM_OK) return rc__;
+            }
             FEASM_HIP(hipMemcpy(b->d_colour_ptrs[m], p->colour_ptr.data(),
                                 sizeof(int64_t) * (nc + 1), hipMemcpyHostToDevice));
             D.colour_ptr = b->d_colour_ptrs[m];
@@ -572,9 +573,10 @@ int create(feasm_batch* b, const feasm_pattern* const* patterns, int64_t count, 
         }
     }
     {
-            const int rc__ = dev_alloc(b->alloc, (void**)&b->d_meshes, sizeof(MeshDesc) * count, nullptr, "batch_create");
-            if (rc__ != FEASM_OK) return rc__;
-        }
+        const int rc__ = dev_alloc(b->alloc, (void**)&b->d_meshes,
+                                   sizeof(MeshDesc) * count, nullptr, "batch_create");
+        if (rc__ != FEASM_OK) return rc__;
+    }
     FEASM_HIP(hipMemcpy(b->d_meshes, descs.data(), sizeof(MeshDesc) * count, hipMemcpyHostToDevice));
     int cus = 0;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
@@ -606,9 +608,10 @@ int create(feasm_batch* b, const feasm_pattern* const* patterns, int64_t count, 
                 L.grid = std::min(L.n_tiles, kGridTilesMax);
             }
             {
-            const int rc__ = dev_alloc(b->alloc, (void**)&L.d_tiles, sizeof(BatchTile) * tl.size(), nullptr, "batch_create");
-            if (rc__ != FEASM_OK) return rc__;
-        }
+                const int rc__ = dev_alloc(b->alloc, (void**)&L.d_tiles,
+                                           sizeof(BatchTile) * tl.size(), nullptr, "batch_create");
+                if (rc__ != FEASM_OK) return rc__;
+            }
             FEASM_HIP(hipMemcpy(L.d_tiles, tl.data(), sizeof(BatchTile) * tl.size(),
                                 hipMemcpyHostToDevice));
             here.push_back(L);
@@ -628,20 +631,23 @@ int create(feasm_batch* b, const feasm_pattern* const* patterns, int64_t count, 
     b->n_zero = (int64_t)zero.size();
     if (!zero.empty()) {
         {
-            const int rc__ = dev_alloc(b->alloc, (void**)&b->d_zero, sizeof(ZeroChunk) * zero.size(), nullptr, "batch_create");
+            const int rc__ = dev_alloc(b->alloc, (void**)&b->d_zero,
+                                       sizeof(ZeroChunk) * zero.size(), nullptr, "batch_create");
             if (rc__ != FEASM_OK) return rc__;
         }
         FEASM_HIP(hipMemcpy(b->d_zero, zero.data(), sizeof(ZeroChunk) * zero.size(),
                             hipMemcpyHostToDevice));
     }
     {
-            const int rc__ = dev_alloc(b->alloc, (void**)&b->d_ke, sizeof(double*) * count, nullptr, "batch_create");
-            if (rc__ != FEASM_OK) return rc__;
-        }
+        const int rc__ = dev_alloc(b->alloc, (void**)&b->d_ke,
+                                   sizeof(double*) * count, nullptr, "batch_create");
+        if (rc__ != FEASM_OK) return rc__;
+    }
     {
-            const int rc__ = dev_alloc(b->alloc, (void**)&b->d_values, sizeof(double*) * count, nullptr, "batch_create");
-            if (rc__ != FEASM_OK) return rc__;
-        }
+        const int rc__ = dev_alloc(b->alloc, (void**)&b->d_values,
+                                   sizeof(double*) * count, nullptr, "batch_create");
+        if (rc__ != FEASM_OK) return rc__;
+    }
     FEASM_HIP(hipMemset(b->d_ke, 0, sizeof(double*) * count));
     FEASM_HIP(hipMemset(b->d_values, 0, sizeof(double*) * count));
     b->h_ke.assign(count, nullptr);
