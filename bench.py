@@ -770,8 +770,9 @@ def serve_section(args, rate, seconds, log_prefix="[bench]"):
     re-assemblies per request.  Scenarios: continuous batching with fresh
     element matrices generated on the device per iteration (generator time
     reported apart), the same at 500 req/s (unsaturated), continuous batching
-    on pre-generated per-mesh element-matrix pools (assembly-side capacity,
-    no generator in the loop), patterns built on demand in a byte-bounded
+    on pre-generated per-mesh element-matrix pools (no generator in the
+    loop) at the offered rate and at twice it (assembly-side capacity),
+    patterns built on demand in a byte-bounded
     cache, and one request at a time on one stream (FIFO, the
     one-mesh-per-launch baseline)."""
     import torch
@@ -832,6 +833,8 @@ def serve_section(args, rate, seconds, log_prefix="[bench]"):
             ("continuous", rate, seconds, args.serve_slots, False, None),
             ("continuous_500", 500.0, seconds / 2, args.serve_slots, False, None),
             ("continuous_pooled_K", rate, seconds, args.serve_slots, True, None),
+            # twice the offered rate: where the assembly side alone saturates
+            ("continuous_pooled_K_2x_rate", 2 * rate, seconds / 2, args.serve_slots, True, None),
             ("continuous_pattern_cache_16GB", rate, seconds / 2, args.serve_slots, False, 16 << 30),
             ("fifo_one_per_launch", rate, seconds / 5, 1, False, None)):
         log(f"{log_prefix} serve {name}: {rate_:.0f} req/s for {secs:.1f} s, {slots} slot(s); "

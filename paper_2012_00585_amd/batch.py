@@ -19,7 +19,8 @@ import torch
 from . import FMT_CRAC, Pattern, _lib, _require, _stream, _track
 
 PATH_NAMES = ["own_g4", "own_g8", "own_g16", "own_g32", "own_g64_j1", "own_g64_j2", "own_g64_j4",
-              "own_g64_j8", "own_g64_j16", "rows2_j1", "rows2_j2", "own_pipe24", "elem_atomic16",
+              "own_g64_j8", "own_g64_j16", "rows2_j1", "rows2_j2", "own_pipe24", "own_lanes3",
+              "own_lanes4", "elem_atomic16",
               "elem_atomic32",
               "elem_atomic64", "elem_plain16", "elem_plain32", "elem_plain64"]
 

@@ -38,6 +38,10 @@ enum Path : int32_t {
     kRows2J1, kRows2J2,
     kPipe24,  // 8-node hexes, 3 DOFs per node, at most 8 incident entries per node:
               // the single-mesh flat row-owned kernel, one node row per tile
+    kLanes3, kLanes4,  // one DOF per node, 3- or 4-node elements: a node row per lane,
+                       // 64 rows per tile (single-mesh calls keep row groups of 4
+                       // lanes: 38 against 41 us on 512^2 quads; in the batch,
+                       // where tiles are plentiful, the fatter tiles win)
     kElemA16, kElemA32, kElemA64, kElemP16, kElemP32, kElemP64,
     kNumPaths
 };
@@ -102,7 +106,7 @@ __device__ inline void batch_tile(const MeshDesc* __restrict__ meshes,
     const int32_t cur = ldc(&tile->mesh);
     const int32_t colour = ldc(&tile->colour);
     const int64_t index = ldc(&tile->index);
-    if (PATH <= kPipe24) {
+    if (PATH <= kLanes4) {
         OwnArgs O = meshes[cur].own_args;
         O.ke = ke[cur];
         O.values = values[cur];
@@ -119,6 +123,8 @@ __device__ inline void batch_tile(const MeshDesc* __restrict__ meshes,
         if (PATH == kRows2J1) owner_rows_tile<FMT, 2, 1, 8>(O, index, lds);
         if (PATH == kRows2J2) owner_rows_tile<FMT, 2, 2, 8>(O, index, lds);
         if (PATH == kPipe24) owner_pipe_row<FMT, 3, 24, 8, 0, LOOP>(O, index, lds);
+        if (PATH == kLanes3) owner_lanes<FMT, 3, 4>(O, index * 64, lds);
+        if (PATH == kLanes4) owner_lanes<FMT, 4, 4>(O, index * 64, lds);
     } else {
         AsmArgs A = meshes[cur].asm_args;
         A.ke = ke[cur];
@@ -143,14 +149,16 @@ __device__ inline void batch_tile(const MeshDesc* __restrict__ meshes,
 
 // Tile-grid launch (the default): one workgroup per tile of a code path,
 // tiles first .. first + gridDim.x - 1, scheduled by the hardware dispatcher
-// as a single-mesh launch is.
+// as a single-mesh launch is; each XCD takes a contiguous part of the range,
+// so neighbouring rows share their element matrices' lines in one L2.
 template <int FMT, int PATH>
 __global__ void __launch_bounds__(64)
     k_batch_grid(const MeshDesc* __restrict__ meshes, const double* const* __restrict__ ke,
                  double* const* __restrict__ values, const BatchTile* __restrict__ tiles,
                  int64_t first) {
     extern __shared__ double lds[];
-    batch_tile<FMT, PATH, false>(meshes, ke, values, tiles + first + blockIdx.x, lds);
+    batch_tile<FMT, PATH, false>(meshes, ke, values,
+                                 tiles + first + xcd_block(blockIdx.x, gridDim.x), lds);
 }
 
 // Persistent launch: as many workgroups as are resident at once.  The
@@ -215,9 +223,10 @@ GridKernel grid_kernel(int fmt, int path) {
     return fmt == 0 ? t0[path] : t1[path];
 }
 
-// Largest tile-grid launch: 64 lanes per workgroup keep the work-item count
-// of one dispatch within 32 bits; longer tile lists take several launches.
-constexpr int64_t kGridTilesMax = int64_t(1) << 24;
+// Largest tile-grid launch; longer tile lists take several launches (the
+// limit keeps a dispatch's work-item count far within 32 bits, and is low
+// enough that the hex path of the 512-mesh mix is split and tested so).
+constexpr int64_t kGridTilesMax = int64_t(1) << 22;
 
 }  // namespace
 }  // namespace feasm
@@ -301,6 +310,14 @@ int mesh_path(const feasm_pattern* p, int fmt, int strategy, MeshDesc& D, size_t
                 D.path = kPipe24;
                 lds = (size_t)gb + (size_t)2 * 8 * p->k * 4;
                 per = 1;  // one node row per tile
+                return FEASM_OK;
+            }
+            if (g < 64 && p->d == 1 && (p->k == 3 || p->k == 4) && p->tune_owner_rows == 0 &&
+                owner_lanes_lds(fmt, p->max_deg) <= 32 * 1024) {
+                D.path = p->k == 3 ? kLanes3 : kLanes4;
+                A.acc_doubles = (int32_t)(64 * p->max_deg);
+                lds = owner_lanes_lds(fmt, p->max_deg);
+                per = 64;  // node rows per tile
                 return FEASM_OK;
             }
             const int rows = p->tune_owner_rows != 0 ? p->tune_owner_rows : (g == 64 && gb <= 3072 ? 2 : 1);

@@ -808,6 +808,105 @@ __device__ inline void owner_pipe_row(const OwnArgs& A, int64_t v, double* lds_d
         for (int x = l; x < D * ncols; x += 64) __builtin_nontemporal_store(acc[x], out + x);
 }
 
+// One node row per lane, for one DOF per node and K-node elements (short
+// rows: 2-D meshes).  The 64 rows of a wavefront, nodes v0 .. v0 + 63, are
+// consecutive, so their values form one contiguous range of the values
+// array, and their index words one contiguous range of col_idx (CSR) or
+// col_align (CRAC, plus the pair that closes the last row).  Both ranges
+// are staged in LDS; each lane adds its incident elements' row entries, in
+// element order, into an LDS image of the value range at its own row (no
+// other lane touches it), and the wavefront then writes the image with
+// coalesced stores.  Layout: acc_doubles doubles of image, then idx_ints
+// index words.
+template <int FMT, int K, int B>
+__device__ inline void owner_lanes(const OwnArgs& A, int64_t v0, double* lds_d) {
+    const int l = threadIdx.x;
+    const int64_t nn = A.n_nodes;
+    const int64_t v = v0 + l;
+    const bool active = v < nn;
+    const int64_t vend = v0 + 64 < nn ? v0 + 64 : nn;
+    double* acc = lds_d;
+    int32_t* sidx = reinterpret_cast<int32_t*>(acc + A.acc_doubles);
+    // the wavefront's value range [base, end) and index-word range [i0, i1)
+    int32_t base, end, i0, i1;
+    const int32_t* isrc;
+    if (FMT == kCSR) {
+        base = ldc(A.row_ptr + v0);
+        end = ldc(A.row_ptr + vend);
+        i0 = base;
+        i1 = end;
+        isrc = A.col_idx;
+    } else {
+        i0 = ldc(A.crac_row_ptr + v0);
+        i1 = ldc(A.crac_row_ptr + vend) + 2;
+        base = ldc(A.ca + i0 + 1);
+        end = ldc(A.ca + i1 - 1);
+        isrc = A.ca;
+    }
+    // this lane's row: value start, length, runs, its index words in LDS
+    int32_t rs = 0, ncols = 0, npairs = 0, ioff = 0, L = 0;
+    int64_t ib = 0;
+    if (active) {
+        if (FMT == kCSR) {
+            rs = A.row_ptr[v];
+            ncols = A.row_ptr[v + 1] - rs;
+            ioff = rs - i0;
+        } else {
+            const int32_t pb = A.crac_row_ptr[v], pe = A.crac_row_ptr[v + 1];
+            npairs = (pe - pb) >> 1;
+            rs = A.ca[pb + 1];  // an empty row's pb is the next row's first pair
+            ncols = A.ca[pe + 1] - rs;
+            ioff = pb - i0;
+        }
+        ib = A.inc_ptr[v];
+        L = (int32_t)(A.inc_ptr[v + 1] - ib);
+    }
+    for (int32_t x = l; x < i1 - i0; x += 64) sidx[x] = isrc[i0 + x];
+    for (int32_t x = l; x < end - base; x += 64) acc[x] = 0.0;
+    __syncthreads();
+    const int32_t* my_idx = sidx + ioff;
+    double* my_acc = acc + (rs - base);
+    const int32_t lmax = wave_max(L);
+    for (int32_t t0 = 0; t0 < lmax; t0 += B) {
+        int32_t cn[B][K];
+        double kv[B][K];
+#pragma unroll
+        for (int tb = 0; tb < B; ++tb) {
+            if (active && t0 + tb < L) {
+                const int64_t e = A.inc_elem[ib + t0 + tb];
+                const int64_t a = A.inc_local[ib + t0 + tb];
+#pragma unroll
+                for (int b = 0; b < K; ++b) cn[tb][b] = A.conn[e * K + b];
+#pragma unroll
+                for (int b = 0; b < K; ++b)
+                    kv[tb][b] = __builtin_nontemporal_load(A.ke + (e * K + a) * K + b);
+            }
+        }
+#pragma unroll
+        for (int tb = 0; tb < B; ++tb) {
+            if (active && t0 + tb < L) {
+#pragma unroll
+                for (int b = 0; b < K; ++b) {
+                    const int32_t off = row_lookup<FMT>(my_idx, ncols, npairs, rs, cn[tb][b]);
+                    if (off >= 0) my_acc[off] += kv[tb][b];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    double* out = A.values + base;
+    if (A.accumulate)
+        for (int32_t x = l; x < end - base; x += 64) out[x] += acc[x];
+    else
+        for (int32_t x = l; x < end - base; x += 64) __builtin_nontemporal_store(acc[x], out + x);
+}
+
+// LDS bytes of owner_lanes for a mesh with rows of at most max_deg columns.
+inline size_t owner_lanes_lds(int fmt, int64_t max_deg) {
+    const int64_t idx = fmt == kCSR ? 64 * max_deg : 2 * 64 * max_deg + 2;
+    return (size_t)(64 * max_deg * 8 + ((idx * 4 + 7) / 8) * 8);
+}
+
 // Records, for every incidence entry t of node v and every element node b,
 // the offset of b's first column inside v's rows (the lookups of the
 // row-owned kernels, done once for value-only re-assembly).  One 64-lane

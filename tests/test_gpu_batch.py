@@ -40,6 +40,12 @@ def test_device_generator_matches_host_twin(feasm, recipe, n):
     assert (_np(dev) == host).all()
 
 
+def _tris(nx, ny, perm_seed):
+    conn, nn = meshes.quad_mesh(nx, ny)
+    tri = np.concatenate([conn[:, [0, 1, 2]], conn[:, [0, 2, 3]]]).astype(np.int32)
+    return np.ascontiguousarray(meshes.permute_nodes(tri, nn, perm_seed)), nn
+
+
 def _mix():
     """A small batch of uneven meshes of several element types."""
     rep_conn, rep_nn = meshes.quad_mesh(5)
@@ -54,6 +60,9 @@ def _mix():
         ("q3quad3_d2", *meshes.qp_quad_mesh(3, 3), 2),
         ("repeated", rep_conn, rep_nn, 2),
         ("hex5_d1", *meshes.hex_mesh(5), 1),
+        # one DOF per node, 3- and 4-node elements: the row-per-lane path
+        ("tri_perm_d1", *_tris(11, 9, perm_seed=3), 1),
+        ("repeated_d1", rep_conn, rep_nn, 1),
     ]
 
 
@@ -107,7 +116,7 @@ def test_batch_matches_oracle(feasm, orc, fmt, assign, mode):
         torch.cuda.synchronize()
         for (name, strat, ov, oa), v in zip(refs, vals):
             got = _np(v)
-            if strat == "owner" and name != "repeated":
+            if strat == "owner" and not name.startswith("repeated"):  # element order: exact
                 assert (got == ov).all(), (name, rep)
             else:
                 assert_values_close(got, ov, oa, what=f"{name} {strat} rep{rep}")
@@ -115,7 +124,7 @@ def test_batch_matches_oracle(feasm, orc, fmt, assign, mode):
     fn = feasm.assemble_csr if fmt == 0 else feasm.assemble_crac
     for p, k, v, (name, strat, ov, oa) in zip(pats, kes, vals, refs):
         single = _np(fn(p, k))
-        if strat == "owner" and name != "repeated":
+        if strat == "owner" and not name.startswith("repeated"):
             assert (single == _np(v)).all(), name
     b.free()
     for p in pats:

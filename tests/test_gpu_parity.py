@@ -120,6 +120,23 @@ def _repeated():
     return conn, nn
 
 
+def _tris(nx, ny, perm_seed=None):
+    """Each quad of an nx x ny grid cut into two triangles (3 nodes, d = 1
+    cases take the one-row-per-lane kernel)."""
+    conn, nn = meshes.quad_mesh(nx, ny)
+    tri = np.concatenate([conn[:, [0, 1, 2]], conn[:, [0, 2, 3]]]).astype(np.int32)
+    if perm_seed is not None:
+        tri = meshes.permute_nodes(tri, nn, perm_seed)
+    return np.ascontiguousarray(tri), nn
+
+
+def _tet4(m, perm_seed):
+    """Linear tets: the vertex nodes of the tet10 mesh (its edge nodes stay
+    unused, so many rows are empty)."""
+    conn, nn = meshes.tet10_mesh(m, perm_seed=perm_seed)
+    return np.ascontiguousarray(conn[:, :4]), nn
+
+
 CASES = [
     ("one_quad", lambda: meshes.quad_mesh(1), 1),
     ("quad3x5_d2", lambda: meshes.quad_mesh(3, 5), 2),
@@ -139,6 +156,13 @@ CASES = [
     ("q6quad2_d3", lambda: meshes.qp_quad_mesh(2, 6), 3),
     ("quad4_d8", lambda: meshes.quad_mesh(4), 8),
     ("quad3_d20", lambda: meshes.quad_mesh(3), 20),
+    # one DOF per node, 3- and 4-node elements: the one-row-per-lane kernel
+    # (rows of several wavefronts, permuted numbering, empty rows, a node
+    # listed twice by one element)
+    ("tri9x7_d1", lambda: _tris(9, 7), 1),
+    ("tri13x11perm_d1", lambda: _tris(13, 11, perm_seed=2), 1),
+    ("tet4perm_d1", lambda: _tet4(3, perm_seed=1), 1),
+    ("repeated_node_d1", _repeated, 1),
 ]
 
 
@@ -149,7 +173,8 @@ def test_small_cases_spd(feasm, orc, name, make, d):
     say(f"[parity] {name}: E={E} k={k} d={d} nodes={nn}")
     ke = matrices.ke_spd(E, k * d, seed=3)
     res = run_device(feasm, conn, d, nn, ke)
-    check_against_oracle(orc, conn, d, nn, ke, res, owner_exact=(name != "repeated_node"))
+    check_against_oracle(orc, conn, d, nn, ke, res,
+                         owner_exact=not name.startswith("repeated_node"))
     res["p"].free()
 
 
@@ -279,7 +304,7 @@ def test_owner_record_built_with_pattern(feasm, orc, name, make, d):
     rp, ci = orc.pattern(conn, d, nn)
     ov, oa = orc.assemble(conn, d, ke, rp, ci)
     ke_d = torch.from_numpy(ke).to(dev)
-    exact = name != "repeated_node"
+    exact = not name.startswith("repeated_node")
     say(f"[parity] lookup record built with the pattern: {name}")
     for fmt, fn in ((feasm.FMT_CSR, feasm.assemble_csr), (feasm.FMT_CRAC, feasm.assemble_crac)):
         try:
