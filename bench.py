@@ -363,6 +363,9 @@ def main():
         # (atomic or coloured) moves, over the same step time; the row-owned
         # step does not move them
         "scatter_method_equivalent_GBps": spec_bytes / (ms_per_step * 1e-3) / 1e9,
+        # rocprofv3-measured HBM bytes of the dominant kernel over its live
+        # duration (null while the counters are stale)
+        "traffic_GBps": traffic / (kernel_ms * 1e-3) / 1e9 if traffic else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_source": os.path.relpath(prof, ROOT) if traffic else None,
@@ -772,9 +775,9 @@ def serve_section(args, rate, seconds, log_prefix="[bench]"):
     reported apart), the same at 500 req/s (unsaturated), continuous batching
     on pre-generated per-mesh element-matrix pools (no generator in the
     loop) at the offered rate and at twice it (assembly-side capacity),
-    patterns built on demand in a byte-bounded
-    cache, and one request at a time on one stream (FIFO, the
-    one-mesh-per-launch baseline)."""
+    patterns built on demand in a byte-bounded cache and in a 1-byte one
+    (nearly every request builds its own), and one request at a time
+    on one stream (FIFO, the one-mesh-per-launch baseline)."""
     import torch
 
     import paper_2012_00585_amd as feasm
@@ -836,6 +839,11 @@ def serve_section(args, rate, seconds, log_prefix="[bench]"):
             # twice the offered rate: where the assembly side alone saturates
             ("continuous_pooled_K_2x_rate", 2 * rate, seconds / 2, args.serve_slots, True, None),
             ("continuous_pattern_cache_16GB", rate, seconds / 2, args.serve_slots, False, 16 << 30),
+            # a 1-byte cache: an idle pattern stays only until the next miss, so
+            # nearly every request builds its pattern (pattern_build + assembly
+            # + 10 re-assemblies, the request recipe taken literally; the
+            # engine reports the hits)
+            ("pattern_build_per_request", rate, seconds / 10, args.serve_slots, False, 1),
             ("fifo_one_per_launch", rate, seconds / 5, 1, False, None)):
         log(f"{log_prefix} serve {name}: {rate_:.0f} req/s for {secs:.1f} s, {slots} slot(s); "
             "warm-up")
