@@ -498,6 +498,7 @@ int create(feasm_batch* b, const feasm_pattern* const* patterns, int64_t count, 
     std::vector<std::vector<std::vector<BatchTile>>> lists;  // [phase][path]
     std::vector<std::vector<double>> work;
     std::vector<std::vector<size_t>> ldsv;
+    std::vector<int64_t> path_per(kNumPaths, 1);  // rows or elements per tile of a path
     auto ensure = [&](int32_t ph) {
         while ((int32_t)lists.size() <= ph) {
             lists.emplace_back(kNumPaths);
@@ -531,6 +532,7 @@ int create(feasm_batch* b, const feasm_pattern* const* patterns, int64_t count, 
         }
         if (rc != FEASM_OK) return rc;
         b->paths[m] = D.path;
+        path_per[D.path] = per;
         AsmArgs& A = D.asm_args;
         A.conn = p->conn;
         A.k = p->k;
@@ -616,9 +618,11 @@ int create(feasm_batch* b, const feasm_pattern* const* patterns, int64_t count, 
                                                                L.lds);
             const int64_t cap = (int64_t)cus * std::max(per_cu, 1);
             if (b->persistent) {
-                // small chunks keep the in-flight rows of an XCD close together;
-                // four tiles per counter pop measured best on the 512-mesh mix
-                L.chunk = std::max<int64_t>(1, std::min<int64_t>(4, L.n_tiles / (cap * 8)));
+                // small chunks keep the in-flight rows of an XCD close together:
+                // about four rows or elements per counter pop (four one-row tiles,
+                // one 64-row tile) measured best on the 512-mesh mix
+                const int64_t want = std::max<int64_t>(1, 4 / path_per[path]);
+                L.chunk = std::max<int64_t>(1, std::min<int64_t>(want, L.n_tiles / (cap * 8)));
                 L.grid = std::max<int64_t>(1, std::min<int64_t>(cap, ceil_div(L.n_tiles, L.chunk)));
             } else {
                 L.chunk = 1;
