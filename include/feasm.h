@@ -85,7 +85,9 @@ enum {
                                    each sum once -- a plain store where the tile holds
                                    every element coupling the two nodes, one atomic add
                                    otherwise */
-    FEASM_SCATTER_COLOURED = 2, /* one launch per colour, plain read-modify-write */
+    FEASM_SCATTER_COLOURED = 2, /* one launch per colour, plain read-modify-write
+                                   (per colour and element-id block, blocks one
+                                   after another: FEASM_TUNE_COLOUR_BLOCKS) */
     FEASM_SCATTER_OWNER = 3,    /* row-owned: each node row is summed by one wavefront
                                    from the incident elements, in element order, and
                                    written once (no atomics, no reset pass) */
@@ -274,6 +276,12 @@ int pattern_colouring(const feasm_pattern* p, const int64_t** colour_ptr,
  *                                   per lane before it gives up (0: 2^20;
  *                                   -1: none, every lane gives up at once,
  *                                   which exercises the give-up path)
+ *   FEASM_TUNE_COLOUR_BLOCKS        handles with colouring: element-id blocks
+ *                                   the coloured scatter runs one after
+ *                                   another, every colour within each block,
+ *                                   1 to 256 (0: the values array's size over
+ *                                   the 256 MiB memory-side cache, rounded);
+ *                                   synchronises the device
  * Returns EINVAL for an unknown key or value.
  */
 enum {
@@ -287,7 +295,8 @@ enum {
     FEASM_TUNE_SPMV_CHUNK = 8,
     FEASM_TUNE_HEX8_PIPE = 9,
     FEASM_TUNE_SPIN_LIMIT = 10,
-    FEASM_TUNE_TILE_CAP = 11
+    FEASM_TUNE_TILE_CAP = 11,
+    FEASM_TUNE_COLOUR_BLOCKS = 12
 };
 int pattern_tune(feasm_pattern* p, int key, int64_t value);
 

@@ -45,6 +45,7 @@ TUNE_SPMV_CHUNK = 8
 TUNE_HEX8_PIPE = 9
 TUNE_SPIN_LIMIT = 10
 TUNE_TILE_CAP = 11
+TUNE_COLOUR_BLOCKS = 12
 
 _HIP_D2D = 3  # hipMemcpyDeviceToDevice
 

@@ -452,11 +452,19 @@ int assemble_impl(const feasm_pattern* p, int fmt, const double* ke, double* val
     // Elements of one colour share no node, so no two of them touch the same
     // value; an element that lists a node twice touches some values twice
     // itself, and then the adds stay atomic.
-    for (int32_t c = 0; c < p->n_colours; ++c) {
-        A.elem_list = p->colour_elems + p->colour_ptr[c];
-        A.count = p->colour_ptr[c + 1] - p->colour_ptr[c];
-        const int rc = launch(fmt, p->has_repeats, A, sh, s);
-        if (rc != FEASM_OK) return rc;
+    // Element block by element block, the colours in order within a block:
+    // consecutive launches then touch the same values rows (set_colour_blocks).
+    const int64_t nb = p->colour_blocks;
+    for (int64_t b = 0; b < nb; ++b) {
+        for (int32_t c = 0; c < p->n_colours; ++c) {
+            const int64_t lo = p->colour_block_ptr[(size_t)c * (nb + 1) + b];
+            const int64_t hi = p->colour_block_ptr[(size_t)c * (nb + 1) + b + 1];
+            if (hi <= lo) continue;
+            A.elem_list = p->colour_elems + lo;
+            A.count = hi - lo;
+            const int rc = launch(fmt, p->has_repeats, A, sh, s);
+            if (rc != FEASM_OK) return rc;
+        }
     }
     return FEASM_OK;
 }
@@ -595,6 +603,13 @@ extern "C" int pattern_tune(feasm_pattern* p, int key, int64_t value) {
                 FEASM_FAIL(FEASM_EINVAL, "pattern_tune: owner blocks per CU must be in [0, 64]");
             p->tune_owner_blocks_per_cu = (int32_t)value;
             return FEASM_OK;
+        }
+        if (key == FEASM_TUNE_COLOUR_BLOCKS) {
+            if (value < 0 || value > 256)
+                FEASM_FAIL(FEASM_EINVAL, "pattern_tune: colour blocks must be in [0, 256]");
+            if (!(p->flags & FEASM_BUILD_COLOUR))
+                FEASM_FAIL(FEASM_EINVAL, "pattern_tune: handle was built without FEASM_BUILD_COLOUR");
+            return feasm::set_colour_blocks(p, value, nullptr);
         }
         if (key == FEASM_TUNE_TILE_CAP) {
             if (value < 0 || value > 64)

@@ -128,6 +128,11 @@ struct feasm_pattern {
     // colouring
     int32_t n_colours = 0;
     std::vector<int64_t> colour_ptr;  // host [n_colours+1]
+    // The coloured scatter runs element block by element block, the colours
+    // in order within each block: block b of colour c is colour_elems
+    // [colour_block_ptr[c*(colour_blocks+1)+b], ...[...+b+1]) (host table).
+    int32_t colour_blocks = 1;
+    std::vector<int64_t> colour_block_ptr;
     int32_t* colour_elems = nullptr;  // dev [n_elem]
     int32_t* elem_colour = nullptr;   // dev [n_elem]
 
@@ -193,6 +198,9 @@ int build_node_order(feasm_pattern* p, hipStream_t s, int64_t* n_light_host);
 
 // Colouring (colour.hip): fills p->elem_colour, colour_elems, colour_ptr, n_colours.
 int build_colouring(feasm_pattern* p, hipStream_t s);
+// Splits every colour's element list into nb element-id blocks (0: by the
+// matrix size) and stores the table of block starts (synchronises s).
+int set_colour_blocks(feasm_pattern* p, int64_t nb, hipStream_t s);
 
 // Element tiles of the atomic scatter (tiles.hip): build_tiles fills the
 // tile arrays of the handle (or leaves n_tiles = 0 when tiles cannot be

@@ -325,6 +325,39 @@ def test_owner_record_built_with_pattern(feasm, orc, name, make, d):
     p.free()
 
 
+def test_colour_blocks(feasm, orc):
+    """The coloured scatter run element block by element block: every block
+    count gives the oracle's values (integer element matrices: exact in any
+    order), on a grid-numbered hex mesh and a permuted tet10 mesh; the knob
+    needs a coloured handle and a count in [0, 256]."""
+    dev = torch.device("cuda:0")
+    for name, (conn, nn), d in (("hex 9x7x5", meshes.hex_mesh(9, 7, 5), 3),
+                                ("tet10 3^3 permuted", meshes.tet10_mesh(3, perm_seed=6), 3)):
+        E, k = conn.shape
+        p = feasm.pattern_build(torch.from_numpy(conn).to(dev), d, nn,
+                                feasm.BUILD_CSR | feasm.BUILD_CRAC | feasm.BUILD_COLOUR)
+        rp, ci = orc.pattern(conn, d, nn)
+        kei = matrices.ke_small_int(E, k * d, seed=13)
+        ov, _ = orc.assemble(conn, d, kei, rp, ci)
+        ke_d = torch.from_numpy(kei).to(dev)
+        for nb in (2, 3, 7, min(E, 256), 256, 1, 0):
+            say(f"[parity] {name}: coloured scatter in {nb} element blocks")
+            p.tune(feasm.TUNE_COLOUR_BLOCKS, nb)
+            for fn in (feasm.assemble_csr, feasm.assemble_crac):
+                v = fn(p, ke_d, scatter=feasm.SCATTER_COLOURED)
+                assert (_np(v) == ov).all(), (name, nb, fn.__name__)
+                fn(p, ke_d, values=v, scatter=feasm.SCATTER_COLOURED | feasm.ACCUMULATE)
+                assert (_np(v) == 2 * ov).all(), (name, nb, fn.__name__, "accumulate")
+        with pytest.raises(feasm.FeasmError):
+            p.tune(feasm.TUNE_COLOUR_BLOCKS, 257)
+        p.free()
+    conn, nn = meshes.quad_mesh(4)
+    p = feasm.pattern_build(torch.from_numpy(conn).to(dev), 1, nn)
+    with pytest.raises(feasm.FeasmError):
+        p.tune(feasm.TUNE_COLOUR_BLOCKS, 2)
+    p.free()
+
+
 def test_error_paths_on_device(feasm):
     dev = torch.device("cuda:0")
     conn, nn = meshes.quad_mesh(3)
