@@ -281,7 +281,8 @@ int pattern_colouring(const feasm_pattern* p, const int64_t** colour_ptr,
  *                                   another, every colour within each block,
  *                                   1 to 256 (0: the values array's size over
  *                                   the 256 MiB memory-side cache, rounded);
- *                                   synchronises the device
+ *                                   reads the colour lists back to the host
+ *                                   (a synchronous copy)
  * Returns EINVAL for an unknown key or value.
  */
 enum {
