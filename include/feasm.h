@@ -143,9 +143,11 @@ enum {
  * row-owned strategy then reads it instead of the element's connectivity
  * row and the search in the owned row, from the first assembly on (without
  * the flag it is built by the first row-owned reassemble_values).  Pays on
- * meshes whose node numbering is scattered (the permuted tet10 mesh); on a
- * mesh numbered along a grid the connectivity rows are cache hits and the
- * record only adds reads.
+ * meshes whose node numbering is scattered (the permuted tet10 mesh) and on
+ * elements with many nodes (tet10; high-order quads, where it makes the
+ * row-owned strategy faster than atomics); on 8-node hexahedra numbered
+ * along a grid the connectivity rows are cache hits and the record only
+ * adds reads.
  *
  * Errors: EINVAL for bad arguments; ERANGE if a node id is out of range
  * (checked on the device, reported before returning); EOVERFLOW for int32
